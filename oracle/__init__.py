@@ -1,0 +1,229 @@
+"""CPU FP64 oracle for the PRTGS transfer path -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  The HIP library and its Python binding never import it,
+and it never imports them; the only code the two sides share is the seeded
+input generator module ``scenegen``.
+
+The brute-force core is plain C (``prtgs_oracle.c``, compiled with gcc and
+OpenMP, loaded with ctypes); relighting is an FP64 einsum and the gradients
+are torch float64 autograd through a separate re-expression of the forward
+(``oracle.grad``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "prtgs_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+# Default cutoffs: 3-sigma hit extent, peaks behind the origin ignored,
+# transmittance below 1e-4 is opaque, no alpha floor, alpha clamped at 0.99.
+DEFAULT_CUT = dict(sigma_cut=3.0, t_min=0.0, T_eps=1e-4, alpha_min=0.0, alpha_max=0.99)
+# Margins inside which an FP32 evaluation may resolve a predicate either way.
+DEFAULT_MARGINS = (1e-6, 3e-5, 3e-6, 1e-3, 1e-5)
+
+
+def build(force: bool = False) -> str:
+    """Compile the C core with gcc (idempotent unless ``force``)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib_handle = None
+
+
+def _lib():
+    global _lib_handle
+    if _lib_handle is None:
+        build()
+        lib = ctypes.CDLL(LIB)
+        lib.ora_splitmix64.restype = ctypes.c_uint64
+        lib.ora_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        _lib_handle = lib
+    return _lib_handle
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _cut_array(cut):
+    c = dict(DEFAULT_CUT)
+    if cut:
+        c.update(cut)
+    return np.array([c["sigma_cut"], c["t_min"], c["T_eps"], c["alpha_min"], c["alpha_max"]], dtype=np.float64)
+
+
+def default_threads() -> int:
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+# ----------------------------------------------------------------------------
+# tables
+# ----------------------------------------------------------------------------
+
+def splitmix64(seed: int, index: int) -> int:
+    return int(_lib().ora_splitmix64(ctypes.c_uint64(seed), ctypes.c_uint64(index)))
+
+
+def grid(S: int):
+    nu, nv = ctypes.c_int(), ctypes.c_int()
+    _lib().ora_grid(ctypes.c_int(S), ctypes.byref(nu), ctypes.byref(nv))
+    return nu.value, nv.value
+
+
+def directions(S: int, seed: int = 0) -> np.ndarray:
+    """[S,3] stratified directions (FP32 values held in FP64)."""
+    out = np.empty((S, 3), dtype=np.float64)
+    _lib().ora_directions(ctypes.c_int(S), ctypes.c_uint64(seed), _p(out))
+    return out
+
+
+def sh_basis(bands: int, dirs) -> np.ndarray:
+    """[S, bands^2] real orthonormal SH at ``dirs`` (normalised inside)."""
+    dirs = _f64(np.atleast_2d(dirs))
+    K = bands * bands
+    out = np.empty((dirs.shape[0], K), dtype=np.float64)
+    lib = _lib()
+    for s in range(dirs.shape[0]):
+        row = np.ascontiguousarray(dirs[s])
+        lib.ora_sh_basis(ctypes.c_int(bands), _p(row), out[s].ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def tables(S: int, seed: int, bands: int):
+    d = directions(S, seed)
+    return d, sh_basis(bands, d)
+
+
+# ----------------------------------------------------------------------------
+# transfer
+# ----------------------------------------------------------------------------
+
+def _scene_arrays(scene):
+    return (_f64(scene["means"]), _f64(scene["quats"]), _f64(scene["log_scales"]),
+            _f64(scene["opacity"]), _f64(scene["normals"]))
+
+
+def direct_transfer(scene, num_dirs, bands, seed=0, cut=None, sources=None, want_vis=False,
+                    want_allow=False, margins=DEFAULT_MARGINS, threads=None, dirs=None, Y=None):
+    """Direct (visibility) transfer t[count, K] of the listed sources.
+
+    Returns dict(t=..., vis=[count,S] or None (-1 marks untraced rays),
+    allow=[count,K] or None).
+    """
+    means, quats, log_scales, opacity, normals = _scene_arrays(scene)
+    n = means.shape[0]
+    if dirs is None:
+        dirs, Y = tables(num_dirs, seed, bands)
+    K = Y.shape[1]
+    src = np.arange(n, dtype=np.int32) if sources is None else np.ascontiguousarray(sources, dtype=np.int32)
+    count = src.shape[0]
+    t = np.empty((count, K))
+    vis = np.empty((count, num_dirs)) if want_vis else None
+    allow = np.empty((count, K)) if want_allow else None
+    mar = np.array(margins, dtype=np.float64) if (want_allow or margins is not None) else None
+    _lib().ora_direct(ctypes.c_int(n), _p(means), _p(quats), _p(log_scales), _p(opacity), _p(normals),
+                      ctypes.c_int(num_dirs), _p(_f64(dirs)), ctypes.c_int(K), _p(_f64(Y)),
+                      _p(_cut_array(cut)), _p(mar), _p(src), ctypes.c_int(count), _p(t), _p(vis),
+                      _p(allow), ctypes.c_int(threads or default_threads()))
+    return dict(t=t, vis=vis, allow=allow)
+
+
+def hit_set(scene, num_dirs, seed=0, cut=None, sources=None, margins=DEFAULT_MARGINS, threads=None):
+    """Sorted indices of every Gaussian hit by a traced ray of ``sources``."""
+    means, quats, log_scales, opacity, normals = _scene_arrays(scene)
+    n = means.shape[0]
+    dirs = directions(num_dirs, seed)
+    src = np.arange(n, dtype=np.int32) if sources is None else np.ascontiguousarray(sources, dtype=np.int32)
+    mark = np.zeros(n, dtype=np.uint8)
+    _lib().ora_hit_set(ctypes.c_int(n), _p(means), _p(quats), _p(log_scales), _p(opacity), _p(normals),
+                       ctypes.c_int(num_dirs), _p(dirs), _p(_cut_array(cut)),
+                       _p(np.array(margins, dtype=np.float64)), _p(src), ctypes.c_int(src.shape[0]),
+                       _p(mark), ctypes.c_int(threads or default_threads()))
+    return np.nonzero(mark)[0].astype(np.int64)
+
+
+def bounce_transfer(scene, num_dirs, bands, t_dir_rows, t_dir_index, allow_dir_rows=None, seed=0,
+                    cut=None, sources=None, want_allow=False, margins=DEFAULT_MARGINS, threads=None):
+    """One-bounce indirect transfer t_ind[count, 3, K] of the listed sources.
+
+    ``t_dir_rows[r]`` is the direct transfer of Gaussian ``t_dir_index[r]``
+    (every Gaussian hit by a traced ray of the sources must be listed).
+    """
+    means, quats, log_scales, opacity, normals = _scene_arrays(scene)
+    albedo = _f64(scene["albedo"])
+    n = means.shape[0]
+    dirs, Y = tables(num_dirs, seed, bands)
+    K = Y.shape[1]
+    slot = np.full(n, -1, dtype=np.int32)
+    slot[np.asarray(t_dir_index)] = np.arange(len(t_dir_index), dtype=np.int32)
+    src = np.arange(n, dtype=np.int32) if sources is None else np.ascontiguousarray(sources, dtype=np.int32)
+    count = src.shape[0]
+    out = np.empty((count, 3, K))
+    allow = np.empty((count, 3, K)) if want_allow else None
+    rows = _f64(t_dir_rows)
+    arows = _f64(allow_dir_rows) if allow_dir_rows is not None else None
+    mar = np.array(margins, dtype=np.float64)
+    missing = _lib().ora_bounce(ctypes.c_int(n), _p(means), _p(quats), _p(log_scales), _p(opacity),
+                                _p(normals), _p(albedo), ctypes.c_int(num_dirs), _p(dirs), ctypes.c_int(K),
+                                _p(_cut_array(cut)), _p(mar), _p(slot), _p(rows), _p(arows), _p(src),
+                                ctypes.c_int(count), _p(out), _p(allow),
+                                ctypes.c_int(threads or default_threads()))
+    if missing:
+        raise ValueError("a hit Gaussian has no direct transfer row")
+    return dict(t=out, allow=allow)
+
+
+def full_transfer(scene, num_dirs, bands, bounces, seed=0, cut=None, sources=None, want_allow=False,
+                  margins=DEFAULT_MARGINS, threads=None):
+    """Transfer of the listed sources: [count, 1, K] (direct) or [count, 3, K]
+    (direct in every channel plus the one-bounce term)."""
+    n = scene["means"].shape[0]
+    src = np.arange(n) if sources is None else np.asarray(sources)
+    d = direct_transfer(scene, num_dirs, bands, seed, cut, src, want_allow=want_allow, margins=margins,
+                        threads=threads)
+    if bounces == 0:
+        return dict(t=d["t"][:, None, :], allow=None if d["allow"] is None else d["allow"][:, None, :])
+    need = hit_set(scene, num_dirs, seed, cut, src, margins, threads)
+    dj = direct_transfer(scene, num_dirs, bands, seed, cut, need, want_allow=True, margins=margins,
+                         threads=threads)
+    b = bounce_transfer(scene, num_dirs, bands, dj["t"], need, dj["allow"], seed, cut, src,
+                        want_allow=want_allow, margins=margins, threads=threads)
+    t = d["t"][:, None, :] + b["t"]
+    allow = None
+    if want_allow:
+        allow = d["allow"][:, None, :] + b["allow"]
+    return dict(t=t, allow=allow, t_dir=d["t"], t_ind=b["t"])
+
+
+# ----------------------------------------------------------------------------
+# relighting (Eq. 14: rendering reduces to a dot product in the SH domain)
+# ----------------------------------------------------------------------------
+
+def relight(transfer, light):
+    """colour[n, b, c] = sum_k T[n, c', k] L[b, c, k], c' = c for RGB transfer,
+    0 for a single-channel one.  FP64."""
+    T = np.asarray(transfer, dtype=np.float64)
+    L = np.asarray(light, dtype=np.float64)
+    if T.ndim == 2:
+        T = T[:, None, :]
+    if T.shape[1] == 1:
+        return np.einsum("nk,bck->nbc", T[:, 0, :], L)
+    return np.einsum("nck,bck->nbc", T, L)
