@@ -1,0 +1,207 @@
+/*
+ * prtgs.h -- C ABI of the MI355X (gfx950) radiance-transfer library for 3D
+ * Gaussian splats (PRTGS, arXiv 2408.03538).
+ *
+ * The library precomputes, for every splat, the diffuse radiance transfer
+ * vector of Sec. 3.2 / Sec. 4.5: the visibility along S directions, traced
+ * from the splat centre through the other 3D Gaussians (Sec. 4.4), times
+ * max(0, n . w), projected onto real spherical harmonics (Eq. 7, 9, 11, 29);
+ * optionally one interreflection bounce (Eq. 20-22, 30-33); relights splats
+ * under many SH light environments with the dot product of Eq. 14; and runs
+ * the adjoint of both.
+ *
+ * Conventions shared by every entry point:
+ *  - Every array pointer is a DEVICE pointer unless the comment says "host".
+ *    Arrays are dense, row-major, 32-bit float unless stated.
+ *  - The caller owns every buffer.  The library allocates no device memory:
+ *    BVH storage and scratch ("workspace") are caller buffers whose sizes come
+ *    from the *_bytes queries.  Workspaces must be 256-byte aligned.
+ *  - Every call only enqueues work on `stream` and returns.  Arguments are
+ *    validated on the host first; on any error nothing is enqueued and the
+ *    status says why (prtgs_last_error() gives a message, per thread).
+ *  - Device-side conditions (non-finite inputs, traversal stack overflow) set
+ *    bits in the 32-bit flag word at byte 0 of the call's workspace.  The
+ *    word is cleared by the call; read it after synchronising the stream.
+ *  - Calls on distinct buffers may run concurrently.
+ */
+#ifndef PRTGS_H
+#define PRTGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PRTGS_ABI_VERSION 1
+
+typedef enum {
+    PRTGS_OK = 0,
+    PRTGS_ERR_INVALID_ARG = 1,        /* bad size, null pointer, out-of-range parameter */
+    PRTGS_ERR_WORKSPACE_TOO_SMALL = 2,/* a caller buffer is smaller than its *_bytes query */
+    PRTGS_ERR_UNSUPPORTED = 3,        /* valid request this version does not implement */
+    PRTGS_ERR_HIP = 4                 /* a HIP runtime call or kernel launch failed */
+} prtgs_status;
+
+typedef enum { PRTGS_F32 = 0, PRTGS_BF16 = 1, PRTGS_F16 = 2 } prtgs_dtype;
+
+/* Device flag bits (flag word at byte 0 of a workspace). */
+#define PRTGS_FLAG_NONFINITE 0x1u       /* a non-finite value reached a kernel */
+#define PRTGS_FLAG_STACK_OVERFLOW 0x2u  /* BVH deeper than the traversal stack */
+#define PRTGS_FLAG_BAD_TREE 0x4u        /* malformed BVH (wrong buffer or n): traversal stopped */
+
+/* The splats (Sec. 3.1, Eq. 1-2; normal Sec. 4.3; albedo Sec. 4.2).
+ * Caller-owned, read-only during calls. */
+typedef struct {
+    int32_t n;                 /* number of Gaussians, >= 1 */
+    const float* means;        /* [n][3] centres */
+    const float* quats;        /* [n][4] rotation (w, x, y, z); normalised inside */
+    const float* log_scales;   /* [n][3] log of the scales S of Eq. 2 */
+    const float* opacity;      /* [n]    learned opacity, in (0, 1] */
+    const float* normals;      /* [n][3] unit normals */
+    const float* albedo;       /* [n][3] diffuse albedo rho; needed only for bounces == 1 */
+} prtgs_gaussians;
+
+/* Parameters of the transfer (Sec. 4.4-4.5).  The cutoffs are the reading of
+ * the paper used throughout: a Gaussian is hit by a ray iff its peak density
+ * along the ray lies at t* > t_min and there d^2 <= sigma_cut^2; then
+ * alpha = min(opacity exp(-d^2/2), alpha_max) (Eq. 27 as read here), ignored
+ * if below alpha_min; transmittance below T_eps counts as fully occluded. */
+typedef struct {
+    int32_t num_dirs;          /* S directions per splat, 1 .. 65536 */
+    int32_t sh_bands;          /* L bands, K = L*L coefficients; 1 .. 4 */
+    uint64_t seed;             /* seed of the stratified direction jitter */
+    int32_t bounces;           /* 0 = direct transfer only, 1 = plus one interreflection bounce */
+    float sigma_cut;           /* 3.0 */
+    float t_min;               /* 0.0 */
+    float T_eps;               /* 1e-4 */
+    float alpha_min;           /* 0.0 */
+    float alpha_max;           /* 0.99 */
+} prtgs_transfer_desc;
+
+/* Gradients (each pointer may be NULL = not wanted).  Accumulated (+=) into
+ * caller-initialised buffers of the shapes of prtgs_gaussians. */
+typedef struct {
+    float* d_means;            /* [n][3] */
+    float* d_quats;            /* [n][4] with respect to the unnormalised quaternion */
+    float* d_log_scales;       /* [n][3] */
+    float* d_opacity;          /* [n] */
+    float* d_normals;          /* [n][3] */
+} prtgs_grads;
+
+int32_t prtgs_abi_version(void);
+const char* prtgs_last_error(void);            /* host string, thread-local, never NULL */
+const char* prtgs_status_string(prtgs_status s);
+
+/* ---------------------------------------------------------------------- */
+/* Direction table (Eq. 8-11 need the SH basis at a set of directions).     */
+/* S stratified equal-area directions: grid n_u x n_v with n_u the largest  */
+/* divisor of S not above floor(sqrt(S)); stratum s = a n_v + b gets        */
+/* z = 1 - 2 (a + xi)/n_u, phi = 2 pi (b + eta)/n_v with xi, eta the top 53 */
+/* bits (scaled by 2^-53) of outputs 2s and 2s+1 of a SplitMix64 stream     */
+/* seeded with `seed`.  Generated in FP64 on the device, rounded to FP32;   */
+/* Y is the real orthonormal SH basis (Condon-Shortley phase, index         */
+/* k = l^2 + l + m) at the normalised FP32 direction, in FP64.              */
+/* Any output pointer may be NULL.  Quadrature weight of each: 4 pi / S.    */
+/* ---------------------------------------------------------------------- */
+prtgs_status prtgs_direction_table(int32_t num_dirs, uint64_t seed, int32_t sh_bands,
+                                   double* dirs64 /* [S][3] */, double* Y64 /* [S][K] */,
+                                   float* dirs32 /* [S][3] */, float* Y32 /* [S][K] */,
+                                   hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Bounding volume hierarchy over the Gaussians' 3-sigma boxes (the paper   */
+/* builds its Gaussian ray tracer on a BVH, Sec. 4.4).  Linear BVH: 30-bit  */
+/* Morton codes of the centres, a stable radix sort, Karras' hierarchy      */
+/* (ties broken by index) and a bottom-up box refit.  The BVH buffer also   */
+/* holds per-splat ray-test records (centre, opacity, whitening matrix      */
+/* diag(1/s) R^T, normal) in leaf order and the leaf-to-splat permutation.   */
+/* The BVH depends on means, quats, log_scales, opacity, normals; rebuild   */
+/* it when any of them changes.  ws: scratch of prtgs_build_workspace_bytes.*/
+/* ---------------------------------------------------------------------- */
+size_t prtgs_bvh_bytes(int32_t n);
+size_t prtgs_build_workspace_bytes(int32_t n);
+prtgs_status prtgs_build_bvh(const prtgs_gaussians* g /* host struct */, void* bvh, size_t bvh_bytes,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Leaf order of a built BVH: order[r] = index of the Gaussian in leaf r (a
+ * copy into caller memory, enqueued on stream). */
+prtgs_status prtgs_bvh_leaf_order(const void* bvh, int32_t n, int32_t* order /* [n] */,
+                                  hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Transfer precompute (Sec. 4.4-4.5; Eq. 7, 9, 29; bounce Eq. 20-22, 30-33).*/
+/* For each source i and direction w_s with c = n_i . w_s > 0 the ray       */
+/* mu_i + t w_s is traced through every Gaussian j != i; V = prod (1 -      */
+/* alpha_j) over hits (0 if below T_eps);                                   */
+/*   t_dir[i][k] = (4 pi / S) sum_s V c Y_k(w_s).                           */
+/* The stored transfer excludes the receiver's rho_i / pi (multiply the     */
+/* relit value by it).  With bounces == 1 the hits of each ray are also     */
+/* walked front to back (by t*, then leaf order), hit j getting weight      */
+/* alpha_j T_j with T_j the transmittance in front of it, until the         */
+/* transmittance drops below T_eps, and                                     */
+/*   transfer[i][c][:] = t_dir[i][:] + (4 pi/S) sum_s c sum_j w_j rho_jc/pi t_dir[j][:].*/
+/* transfer: [n][C][K], C = 1 (bounces 0) or 3 (bounces 1), written for the */
+/* selected sources only.  Sources are selected by leaf rank: those in     */
+/* leaf positions [first, first + count) (chunked or resumable runs; with  */
+/* bounces == 1 the range must be the whole scene).  vis (may be NULL):     */
+/* [n][S] visibility of every ray of the selected sources, -1 for rays with */
+/* c <= 0 (not traced).  ws: prtgs_transfer_workspace_bytes.                */
+/* ---------------------------------------------------------------------- */
+size_t prtgs_transfer_workspace_bytes(const prtgs_transfer_desc* d /* host */, int32_t n);
+prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g /* host */, const void* bvh,
+                                       const prtgs_transfer_desc* d /* host */, int32_t first,
+                                       int32_t count, float* transfer, float* vis, void* ws,
+                                       size_t ws_bytes, hipStream_t stream);
+
+/* Round a float32 array to bf16 or f16 storage (round to nearest even),
+ * e.g. transfer vectors before relighting.  dst has `count` 2-byte values. */
+prtgs_status prtgs_pack(int64_t count, const float* src, void* dst, prtgs_dtype dtype,
+                        hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Relighting (Eq. 14, Eq. 41 for a vector transfer): per splat and light   */
+/* environment the outgoing value is the dot product of transfer and light  */
+/* SH,  colour[i][b][c] = sum_k transfer[i][c'][k] light[b][c][k],  with    */
+/* c' = c if C == 3 else 0.  transfer [n][C][K] in t_dtype (F32, BF16, F16);*/
+/* light [B][3][K] F32; colour [n][B][3] in out_dtype (F32 or F16).  The    */
+/* 16-bit path runs on MFMA with FP32 accumulation and the light split into */
+/* a high and a low bf16/f16 part, so its error is set by the storage of     */
+/* transfer and colour.  K in {1, 4, 9, 16}, C in {1, 3}, 1 <= B <= 256.      */
+/* ---------------------------------------------------------------------- */
+prtgs_status prtgs_relight(int32_t n, int32_t K, int32_t C, const void* transfer, prtgs_dtype t_dtype,
+                           int32_t B, const float* light, void* colour, prtgs_dtype out_dtype,
+                           hipStream_t stream);
+
+/* Adjoint of prtgs_relight for F32 transfer and colour:
+ *   d_transfer[i][c'][k] (+)= sum_b sum_{c -> c'} d_colour[i][b][c] light[b][c][k]  (overwritten)
+ *   d_light[b][c][k]      = sum_i d_colour[i][b][c] transfer[i][c'][k]            (overwritten)
+ * Either output may be NULL.  ws: prtgs_relight_backward_workspace_bytes. */
+size_t prtgs_relight_backward_workspace_bytes(int32_t n, int32_t K, int32_t C, int32_t B);
+prtgs_status prtgs_relight_backward(int32_t n, int32_t K, int32_t C, const float* transfer, int32_t B,
+                                    const float* light, const float* d_colour, float* d_transfer,
+                                    float* d_light, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Adjoint of the direct transfer (bounces == 0): given d_transfer [n][1][K]*/
+/* = dLoss/dt_dir, accumulates dLoss/d(means, quats, log_scales, opacity,   */
+/* normals) into `grads`.  Every ray is traced again (hit lists are not     */
+/* stored); the gradient is that of the piecewise-smooth forward with the   */
+/* hit, hemisphere and opacity-cutoff decisions held fixed.  Atomic         */
+/* accumulation: summation order, hence the last bits, may vary between     */
+/* runs.  ws: prtgs_transfer_backward_workspace_bytes.                      */
+/* ---------------------------------------------------------------------- */
+size_t prtgs_transfer_backward_workspace_bytes(const prtgs_transfer_desc* d /* host */, int32_t n);
+prtgs_status prtgs_transfer_backward(const prtgs_gaussians* g /* host */, const void* bvh,
+                                     const prtgs_transfer_desc* d /* host */, const float* d_transfer,
+                                     const prtgs_grads* grads /* host struct */, void* ws,
+                                     size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRTGS_H */

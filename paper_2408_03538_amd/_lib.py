@@ -1,0 +1,93 @@
+"""ctypes declarations of the C ABI in include/prtgs.h."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libprtgs.so")
+
+PRTGS_OK = 0
+STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "unsupported", 4: "HIP error"}
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
+FLAG_NONFINITE = 0x1
+FLAG_STACK_OVERFLOW = 0x2
+FLAG_BAD_TREE = 0x4
+
+c_size_t = ctypes.c_size_t
+c_void_p = ctypes.c_void_p
+c_int32 = ctypes.c_int32
+c_int64 = ctypes.c_int64
+c_uint64 = ctypes.c_uint64
+c_float = ctypes.c_float
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("means", c_void_p), ("quats", c_void_p), ("log_scales", c_void_p),
+                ("opacity", c_void_p), ("normals", c_void_p), ("albedo", c_void_p)]
+
+
+class TransferDesc(ctypes.Structure):
+    _fields_ = [("num_dirs", c_int32), ("sh_bands", c_int32), ("seed", c_uint64), ("bounces", c_int32),
+                ("sigma_cut", c_float), ("t_min", c_float), ("T_eps", c_float), ("alpha_min", c_float),
+                ("alpha_max", c_float)]
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [("d_means", c_void_p), ("d_quats", c_void_p), ("d_log_scales", c_void_p),
+                ("d_opacity", c_void_p), ("d_normals", c_void_p)]
+
+
+# name: (restype, argtypes)
+SIGNATURES = {
+    "prtgs_abi_version": (c_int32, []),
+    "prtgs_last_error": (ctypes.c_char_p, []),
+    "prtgs_status_string": (ctypes.c_char_p, [c_int32]),
+    "prtgs_direction_table": (c_int32, [c_int32, c_uint64, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p]),
+    "prtgs_bvh_bytes": (c_size_t, [c_int32]),
+    "prtgs_build_workspace_bytes": (c_size_t, [c_int32]),
+    "prtgs_build_bvh": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]),
+    "prtgs_bvh_leaf_order": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "prtgs_transfer_workspace_bytes": (c_size_t, [ctypes.POINTER(TransferDesc), c_int32]),
+    "prtgs_precompute_transfer": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, ctypes.POINTER(TransferDesc),
+                                            c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "prtgs_pack": (c_int32, [c_int64, c_void_p, c_void_p, c_int32, c_void_p]),
+    "prtgs_relight": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int32, c_int32, c_void_p, c_void_p,
+                                c_int32, c_void_p]),
+    "prtgs_relight_backward_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32, c_int32]),
+    "prtgs_relight_backward": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int32, c_void_p, c_void_p,
+                                         c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "prtgs_transfer_backward_workspace_bytes": (c_size_t, [ctypes.POINTER(TransferDesc), c_int32]),
+    "prtgs_transfer_backward": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, ctypes.POINTER(TransferDesc),
+                                          c_void_p, ctypes.POINTER(Grads), c_void_p, c_size_t, c_void_p]),
+}
+
+_handle = None
+
+
+def load():
+    """Loads the built library; raises if it has not been built."""
+    global _handle
+    if _handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2408_03538_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _handle = lib
+    return _handle
+
+
+class PrtgsError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def check(status: int):
+    if status != PRTGS_OK:
+        msg = load().prtgs_last_error()
+        raise PrtgsError(status, msg.decode() if msg else "")

@@ -1,0 +1,282 @@
+"""Python binding of the PRTGS HIP library: argument marshalling only.
+
+Every function here takes and returns torch tensors on the GPU, allocates the
+caller-side buffers the C ABI asks for (BVH storage, workspaces, outputs) and
+passes raw device pointers plus the current HIP stream to the library.  No
+step of the computation runs in Python or in torch.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib
+
+F32 = torch.float32
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _alloc(nbytes: int, device) -> torch.Tensor:
+    buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    if buf.data_ptr() % 256:
+        raise RuntimeError("device allocation is not 256-byte aligned")
+    return buf
+
+
+def _dev_f32(x, device, shape=None):
+    t = torch.as_tensor(x, dtype=F32, device=device).contiguous()
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return t
+
+
+@dataclass
+class Scene:
+    """Gaussian splats on the GPU (float32, contiguous)."""
+    means: torch.Tensor
+    quats: torch.Tensor
+    log_scales: torch.Tensor
+    opacity: torch.Tensor
+    normals: torch.Tensor
+    albedo: torch.Tensor | None = None
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @property
+    def device(self):
+        return self.means.device
+
+    @staticmethod
+    def from_arrays(arrays: dict, device="cuda") -> "Scene":
+        n = len(arrays["means"])
+        return Scene(
+            means=_dev_f32(arrays["means"], device, (n, 3)),
+            quats=_dev_f32(arrays["quats"], device, (n, 4)),
+            log_scales=_dev_f32(arrays["log_scales"], device, (n, 3)),
+            opacity=_dev_f32(arrays["opacity"], device, (n,)),
+            normals=_dev_f32(arrays["normals"], device, (n, 3)),
+            albedo=_dev_f32(arrays["albedo"], device, (n, 3)) if arrays.get("albedo") is not None else None,
+        )
+
+    def c_struct(self) -> _lib.Gaussians:
+        for name in ("means", "quats", "log_scales", "opacity", "normals"):
+            t = getattr(self, name)
+            if t.dtype != F32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError(f"{name} must be a contiguous float32 GPU tensor")
+        return _lib.Gaussians(self.n, self.means.data_ptr(), self.quats.data_ptr(), self.log_scales.data_ptr(),
+                              self.opacity.data_ptr(), self.normals.data_ptr(),
+                              self.albedo.data_ptr() if self.albedo is not None else None)
+
+
+@dataclass
+class TransferParams:
+    """Transfer parameters (directions, SH bands, bounce, cutoffs)."""
+    num_dirs: int = 64
+    sh_bands: int = 3
+    seed: int = 0
+    bounces: int = 0
+    sigma_cut: float = 3.0
+    t_min: float = 0.0
+    T_eps: float = 1e-4
+    alpha_min: float = 0.0
+    alpha_max: float = 0.99
+
+    @property
+    def K(self) -> int:
+        return self.sh_bands * self.sh_bands
+
+    @property
+    def channels(self) -> int:
+        return 3 if self.bounces else 1
+
+    def c_struct(self) -> _lib.TransferDesc:
+        return _lib.TransferDesc(self.num_dirs, self.sh_bands, self.seed, self.bounces, self.sigma_cut, self.t_min,
+                                 self.T_eps, self.alpha_min, self.alpha_max)
+
+    def cut(self) -> dict:
+        return dict(sigma_cut=self.sigma_cut, t_min=self.t_min, T_eps=self.T_eps, alpha_min=self.alpha_min,
+                    alpha_max=self.alpha_max)
+
+
+@dataclass
+class Bvh:
+    buffer: torch.Tensor
+    n: int
+    flags: torch.Tensor = field(repr=False, default=None)   # build workspace (flag word at byte 0)
+
+    def leaf_order(self) -> torch.Tensor:
+        out = torch.empty(self.n, dtype=torch.int32, device=self.buffer.device)
+        _lib.check(_lib.load().prtgs_bvh_leaf_order(_ptr(self.buffer), self.n, _ptr(out), _stream()))
+        return out
+
+
+def read_flags(ws: torch.Tensor) -> int:
+    """Device flag word of a workspace (synchronises with the stream)."""
+    return int(ws[:4].view(torch.int32).item())
+
+
+def check_flags(ws: torch.Tensor, what: str = "kernel"):
+    f = read_flags(ws)
+    if f & _lib.FLAG_NONFINITE:
+        raise FloatingPointError(f"{what}: a non-finite input reached the device")
+    if f & _lib.FLAG_STACK_OVERFLOW:
+        raise RuntimeError(f"{what}: BVH deeper than the traversal stack")
+    if f & _lib.FLAG_BAD_TREE:
+        raise RuntimeError(f"{what}: malformed BVH (buffer built for another scene?)")
+
+
+# ----------------------------------------------------------------------------
+# entry points (same names as the C ABI, without the prefix)
+# ----------------------------------------------------------------------------
+
+def abi_version() -> int:
+    return int(_lib.load().prtgs_abi_version())
+
+
+def direction_table(num_dirs: int, seed: int, sh_bands: int, device="cuda"):
+    """FP64 and FP32 direction / SH-basis tables computed on the device."""
+    K = sh_bands * sh_bands
+    d64 = torch.empty((num_dirs, 3), dtype=torch.float64, device=device)
+    y64 = torch.empty((num_dirs, K), dtype=torch.float64, device=device)
+    d32 = torch.empty((num_dirs, 3), dtype=F32, device=device)
+    y32 = torch.empty((num_dirs, K), dtype=F32, device=device)
+    _lib.check(_lib.load().prtgs_direction_table(num_dirs, seed, sh_bands, _ptr(d64), _ptr(y64), _ptr(d32), _ptr(y32),
+                                                 _stream()))
+    return d64, y64, d32, y32
+
+
+def build_bvh(scene: Scene, check: bool = False) -> Bvh:
+    lib = _lib.load()
+    g = scene.c_struct()
+    nbytes = lib.prtgs_bvh_bytes(scene.n)
+    wbytes = lib.prtgs_build_workspace_bytes(scene.n)
+    buf = _alloc(nbytes, scene.device)
+    ws = _alloc(wbytes, scene.device)
+    _lib.check(lib.prtgs_build_bvh(ctypes.byref(g), _ptr(buf), nbytes, _ptr(ws), wbytes, _stream()))
+    bvh = Bvh(buf, scene.n, ws)
+    if check:
+        check_flags(ws, "build_bvh")
+    return bvh
+
+
+class Workspace:
+    """A reusable device workspace that grows on demand."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != torch.device(device):
+            self.buf = _alloc(nbytes, device)
+        return self.buf
+
+
+def precompute_transfer(scene: Scene, bvh: Bvh, params: TransferParams, first: int = 0, count: int | None = None,
+                        out: torch.Tensor | None = None, want_vis: bool = False, workspace: Workspace | None = None,
+                        check: bool = False):
+    """Transfer vectors [n, C, K] (C = 3 with a bounce) of the sources in leaf
+    positions [first, first + count); optionally the per-ray visibility."""
+    lib = _lib.load()
+    n = scene.n
+    count = n - first if count is None else count
+    g = scene.c_struct()
+    d = params.c_struct()
+    wbytes = lib.prtgs_transfer_workspace_bytes(ctypes.byref(d), n)
+    if wbytes == 0:
+        raise _lib.PrtgsError(1, "invalid transfer parameters")
+    ws = (workspace or Workspace()).get(wbytes, scene.device)
+    if out is None:
+        out = torch.zeros((n, params.channels, params.K), dtype=F32, device=scene.device)
+    vis = torch.full((n, params.num_dirs), float("nan"), dtype=F32, device=scene.device) if want_vis else None
+    _lib.check(lib.prtgs_precompute_transfer(ctypes.byref(g), _ptr(bvh.buffer), ctypes.byref(d), first, count,
+                                             _ptr(out), _ptr(vis), _ptr(ws), ws.numel(), _stream()))
+    if check:
+        check_flags(ws, "precompute_transfer")
+    return (out, vis) if want_vis else out
+
+
+def pack(x: torch.Tensor, dtype: str) -> torch.Tensor:
+    """float32 -> bf16 / f16 storage with round-to-nearest-even."""
+    tdt = {"bf16": torch.bfloat16, "f16": torch.float16}[dtype]
+    x = x.contiguous()
+    if x.dtype != F32:
+        raise ValueError("pack expects float32")
+    out = torch.empty(x.shape, dtype=tdt, device=x.device)
+    _lib.check(_lib.load().prtgs_pack(x.numel(), _ptr(x), _ptr(out), _lib.DTYPES[dtype], _stream()))
+    return out
+
+
+_TORCH_TO_DT = {torch.float32: "f32", torch.bfloat16: "bf16", torch.float16: "f16"}
+
+
+def relight(transfer: torch.Tensor, light: torch.Tensor, out_dtype: str = "f32", out: torch.Tensor | None = None):
+    """colour [n, B, 3] = transfer [n, C, K] . light [B, 3, K] (Eq. 14)."""
+    if transfer.dim() != 3 or light.dim() != 3 or light.shape[1] != 3:
+        raise ValueError("transfer must be [n, C, K] and light [B, 3, K]")
+    n, C, K = transfer.shape
+    B = light.shape[0]
+    if light.shape[2] != K:
+        raise ValueError("transfer and light disagree on K")
+    transfer = transfer.contiguous()
+    light = light.to(F32).contiguous()
+    odt = {"f32": torch.float32, "f16": torch.float16}[out_dtype]
+    if out is None:
+        out = torch.empty((n, B, 3), dtype=odt, device=transfer.device)
+    _lib.check(_lib.load().prtgs_relight(n, K, C, _ptr(transfer), _lib.DTYPES[_TORCH_TO_DT[transfer.dtype]], B,
+                                         _ptr(light), _ptr(out), _lib.DTYPES[out_dtype], _stream()))
+    return out
+
+
+def relight_backward(transfer: torch.Tensor, light: torch.Tensor, d_colour: torch.Tensor, want_dT=True, want_dL=True):
+    lib = _lib.load()
+    n, C, K = transfer.shape
+    B = light.shape[0]
+    transfer = transfer.to(F32).contiguous()
+    light = light.to(F32).contiguous()
+    d_colour = d_colour.to(F32).contiguous()
+    dT = torch.empty_like(transfer) if want_dT else None
+    dL = torch.empty_like(light) if want_dL else None
+    wbytes = lib.prtgs_relight_backward_workspace_bytes(n, K, C, B)
+    ws = _alloc(wbytes, transfer.device)
+    _lib.check(lib.prtgs_relight_backward(n, K, C, _ptr(transfer), B, _ptr(light), _ptr(d_colour), _ptr(dT), _ptr(dL),
+                                          _ptr(ws), wbytes, _stream()))
+    return dT, dL
+
+
+def transfer_backward(scene: Scene, bvh: Bvh, params: TransferParams, d_transfer: torch.Tensor,
+                      grads: dict | None = None, workspace: Workspace | None = None, check: bool = False) -> dict:
+    """dLoss/d(means, quats, log_scales, opacity, normals) from dLoss/dtransfer
+    (direct transfer, [n, 1, K]); accumulated into ``grads`` if given."""
+    lib = _lib.load()
+    n = scene.n
+    dev = scene.device
+    if grads is None:
+        grads = dict(means=torch.zeros((n, 3), dtype=F32, device=dev), quats=torch.zeros((n, 4), dtype=F32, device=dev),
+                     log_scales=torch.zeros((n, 3), dtype=F32, device=dev),
+                     opacity=torch.zeros((n,), dtype=F32, device=dev),
+                     normals=torch.zeros((n, 3), dtype=F32, device=dev))
+    g = scene.c_struct()
+    d = params.c_struct()
+    gr = _lib.Grads(*(grads[k].data_ptr() if grads.get(k) is not None else None
+                      for k in ("means", "quats", "log_scales", "opacity", "normals")))
+    wbytes = lib.prtgs_transfer_backward_workspace_bytes(ctypes.byref(d), n)
+    if wbytes == 0:
+        raise _lib.PrtgsError(1, "invalid transfer parameters")
+    ws = (workspace or Workspace()).get(wbytes, dev)
+    dt = d_transfer.to(F32).contiguous()
+    _lib.check(lib.prtgs_transfer_backward(ctypes.byref(g), _ptr(bvh.buffer), ctypes.byref(d), _ptr(dt),
+                                           ctypes.byref(gr), _ptr(ws), ws.numel(), _stream()))
+    if check:
+        check_flags(ws, "transfer_backward")
+    return grads

@@ -1,0 +1,345 @@
+// C ABI of the library: host-side validation, workspace carving and dispatch
+// to the kernels.  No device memory is allocated here.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "common.hpp"
+
+namespace prtgs {
+
+void stratified_grid(int S, int* nu, int* nv);
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+prtgs_status fail(prtgs_status s, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+prtgs_status ok()
+{
+    g_err[0] = '\0';
+    return PRTGS_OK;
+}
+
+prtgs_status hip_status(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return ok();
+    return fail(PRTGS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+constexpr int kMaxN = 1 << 30;
+
+prtgs_status check_gaussians(const prtgs_gaussians* g, bool need_albedo)
+{
+    if (!g) return fail(PRTGS_ERR_INVALID_ARG, "gaussians struct is NULL");
+    if (g->n < 1 || g->n > kMaxN) return fail(PRTGS_ERR_INVALID_ARG, "n = %d outside [1, 2^30]", g->n);
+    if (!g->means || !g->quats || !g->log_scales || !g->opacity || !g->normals)
+        return fail(PRTGS_ERR_INVALID_ARG, "a Gaussian attribute pointer is NULL");
+    if (need_albedo && !g->albedo) return fail(PRTGS_ERR_INVALID_ARG, "albedo is NULL but a bounce was requested");
+    return PRTGS_OK;
+}
+
+prtgs_status check_desc(const prtgs_transfer_desc* d)
+{
+    if (!d) return fail(PRTGS_ERR_INVALID_ARG, "transfer desc is NULL");
+    if (d->num_dirs < 1 || d->num_dirs > 65536)
+        return fail(PRTGS_ERR_INVALID_ARG, "num_dirs = %d outside [1, 65536]", d->num_dirs);
+    if (d->sh_bands < 1 || d->sh_bands > 4)
+        return fail(PRTGS_ERR_INVALID_ARG, "sh_bands = %d outside [1, 4]", d->sh_bands);
+    if (d->bounces != 0 && d->bounces != 1) return fail(PRTGS_ERR_INVALID_ARG, "bounces = %d not 0 or 1", d->bounces);
+    if (!(d->sigma_cut > 0.0f && d->sigma_cut <= kBoxSigma))
+        return fail(PRTGS_ERR_INVALID_ARG, "sigma_cut = %g outside (0, 3] (BVH boxes are 3-sigma)", d->sigma_cut);
+    if (!std::isfinite(d->t_min) || d->t_min < 0.0f) return fail(PRTGS_ERR_INVALID_ARG, "t_min must be finite and >= 0");
+    if (!(d->T_eps >= 0.0f && d->T_eps < 1.0f)) return fail(PRTGS_ERR_INVALID_ARG, "T_eps outside [0, 1)");
+    if (!(d->alpha_max > 0.0f && d->alpha_max <= 0.999f))
+        return fail(PRTGS_ERR_INVALID_ARG, "alpha_max outside (0, 0.999]");
+    if (!(d->alpha_min >= 0.0f && d->alpha_min <= d->alpha_max))
+        return fail(PRTGS_ERR_INVALID_ARG, "alpha_min outside [0, alpha_max]");
+    return PRTGS_OK;
+}
+
+struct TransferWs {
+    size_t dirs, Y, tdir, total;
+};
+
+TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
+{
+    TransferWs w;
+    int K = d.sh_bands * d.sh_bands;
+    size_t off = kFlagBytes;
+    w.dirs = off;
+    off += align256(sizeof(float) * 3 * (size_t)d.num_dirs);
+    w.Y = off;
+    off += align256(sizeof(float) * (size_t)K * (size_t)d.num_dirs);
+    w.tdir = off;
+    if (d.bounces) off += align256(sizeof(float) * (size_t)K * (size_t)n);
+    w.total = off;
+    return w;
+}
+
+HitParams hit_params(const prtgs_transfer_desc& d)
+{
+    HitParams h;
+    h.cut2 = d.sigma_cut * d.sigma_cut;
+    h.t_min = d.t_min;
+    h.T_eps = d.T_eps;
+    h.alpha_min = d.alpha_min;
+    h.alpha_max = d.alpha_max;
+    return h;
+}
+
+}  // namespace
+}  // namespace prtgs
+
+using namespace prtgs;
+
+extern "C" {
+
+int32_t prtgs_abi_version(void) { return PRTGS_ABI_VERSION; }
+
+const char* prtgs_last_error(void) { return g_err; }
+
+const char* prtgs_status_string(prtgs_status s)
+{
+    switch (s) {
+        case PRTGS_OK: return "ok";
+        case PRTGS_ERR_INVALID_ARG: return "invalid argument";
+        case PRTGS_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case PRTGS_ERR_UNSUPPORTED: return "unsupported";
+        case PRTGS_ERR_HIP: return "HIP error";
+    }
+    return "unknown status";
+}
+
+prtgs_status prtgs_direction_table(int32_t num_dirs, uint64_t seed, int32_t sh_bands, double* dirs64, double* Y64,
+                                   float* dirs32, float* Y32, hipStream_t stream)
+{
+    if (num_dirs < 1 || num_dirs > 65536) return fail(PRTGS_ERR_INVALID_ARG, "num_dirs = %d outside [1, 65536]", num_dirs);
+    if (sh_bands < 1 || sh_bands > 8) return fail(PRTGS_ERR_INVALID_ARG, "sh_bands = %d outside [1, 8]", sh_bands);
+    if (!dirs64 && !Y64 && !dirs32 && !Y32) return ok();
+    return hip_status(launch_direction_table(num_dirs, seed, sh_bands, dirs64, Y64, dirs32, Y32, stream),
+                      "direction table");
+}
+
+size_t prtgs_bvh_bytes(int32_t n) { return n < 1 ? 0 : bvh_layout(n).total; }
+
+size_t prtgs_build_workspace_bytes(int32_t n) { return n < 1 ? 0 : build_workspace_bytes(n); }
+
+prtgs_status prtgs_build_bvh(const prtgs_gaussians* g, void* bvh, size_t bvh_bytes, void* ws, size_t ws_bytes,
+                             hipStream_t stream)
+{
+    prtgs_status st = check_gaussians(g, false);
+    if (st != PRTGS_OK) return st;
+    if (!bvh || !ws) return fail(PRTGS_ERR_INVALID_ARG, "bvh or workspace is NULL");
+    if (!aligned256(bvh) || !aligned256(ws)) return fail(PRTGS_ERR_INVALID_ARG, "bvh and workspace must be 256-byte aligned");
+    if (bvh_bytes < prtgs_bvh_bytes(g->n))
+        return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL, "bvh buffer has %zu bytes, needs %zu", bvh_bytes, prtgs_bvh_bytes(g->n));
+    if (ws_bytes < prtgs_build_workspace_bytes(g->n))
+        return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes,
+                    prtgs_build_workspace_bytes(g->n));
+    unsigned* flags = static_cast<unsigned*>(ws);
+    hipError_t e = fill_u32(flags, 0u, 1, stream);
+    if (e == hipSuccess) e = launch_build_bvh(*g, bvh, ws, flags, stream);
+    return hip_status(e, "build bvh");
+}
+
+prtgs_status prtgs_bvh_leaf_order(const void* bvh, int32_t n, int32_t* order, hipStream_t stream)
+{
+    if (!bvh || !order) return fail(PRTGS_ERR_INVALID_ARG, "bvh or order is NULL");
+    if (n < 1 || n > kMaxN) return fail(PRTGS_ERR_INVALID_ARG, "n = %d outside [1, 2^30]", n);
+    return hip_status(launch_leaf_order(bvh, n, order, stream), "leaf order copy");
+}
+
+size_t prtgs_transfer_workspace_bytes(const prtgs_transfer_desc* d, int32_t n)
+{
+    if (!d || n < 1 || check_desc(d) != PRTGS_OK) return 0;
+    return transfer_ws_layout(*d, n).total;
+}
+
+prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g, const void* bvh, const prtgs_transfer_desc* d,
+                                       int32_t first, int32_t count, float* transfer, float* vis, void* ws,
+                                       size_t ws_bytes, hipStream_t stream)
+{
+    prtgs_status st = check_desc(d);
+    if (st != PRTGS_OK) return st;
+    st = check_gaussians(g, d->bounces == 1);
+    if (st != PRTGS_OK) return st;
+    const int n = g->n;
+    if (!bvh || !ws) return fail(PRTGS_ERR_INVALID_ARG, "bvh or workspace is NULL");
+    if (!aligned256(bvh) || !aligned256(ws)) return fail(PRTGS_ERR_INVALID_ARG, "bvh and workspace must be 256-byte aligned");
+    if (first < 0 || count < 0 || (int64_t)first + count > n)
+        return fail(PRTGS_ERR_INVALID_ARG, "source range [%d, %d + %d) outside [0, %d)", first, first, count, n);
+    if (d->bounces == 1 && (first != 0 || count != n))
+        return fail(PRTGS_ERR_INVALID_ARG, "a bounce needs every source's direct transfer: use first = 0, count = n");
+    if (count > 0 && !transfer) return fail(PRTGS_ERR_INVALID_ARG, "transfer is NULL");
+    TransferWs W = transfer_ws_layout(*d, n);
+    if (ws_bytes < W.total)
+        return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes, W.total);
+
+    char* w = static_cast<char*>(ws);
+    unsigned* flags = reinterpret_cast<unsigned*>(w);
+    float* dirs = reinterpret_cast<float*>(w + W.dirs);
+    float* Y = reinterpret_cast<float*>(w + W.Y);
+    hipError_t e = fill_u32(flags, 0u, 1, stream);
+    if (e == hipSuccess)
+        e = launch_direction_table(d->num_dirs, d->seed, d->sh_bands, nullptr, nullptr, dirs, Y, stream);
+    if (e != hipSuccess) return hip_status(e, "direction table");
+    if (count == 0) return ok();
+
+    const BvhLayout L = bvh_layout(n);
+    const char* b = static_cast<const char*>(bvh);
+    TransferArgs a;
+    a.nodes = reinterpret_cast<const Node*>(b + L.nodes);
+    a.prims = reinterpret_cast<const Prim*>(b + L.prims);
+    a.order = reinterpret_cast<const int32_t*>(b + L.order);
+    a.dirs = dirs;
+    a.Y = Y;
+    a.S = d->num_dirs;
+    a.K = d->sh_bands * d->sh_bands;
+    a.n = n;
+    a.first = first;
+    a.count = count;
+    a.channels = d->bounces ? 3 : 1;
+    a.hp = hit_params(*d);
+    a.transfer = transfer;
+    a.vis = vis;
+    a.tdir_sorted = d->bounces ? reinterpret_cast<float*>(w + W.tdir) : nullptr;
+    a.albedo = g->albedo;
+    a.flags = flags;
+    e = launch_transfer_direct(a, stream);
+    if (e != hipSuccess) return hip_status(e, "direct transfer");
+    if (d->bounces) {
+        e = launch_transfer_bounce(a, stream);
+        if (e != hipSuccess) return hip_status(e, "bounce transfer");
+    }
+    return ok();
+}
+
+prtgs_status prtgs_pack(int64_t count, const float* src, void* dst, prtgs_dtype dtype, hipStream_t stream)
+{
+    if (count < 0) return fail(PRTGS_ERR_INVALID_ARG, "count < 0");
+    if (count == 0) return ok();
+    if (!src || !dst) return fail(PRTGS_ERR_INVALID_ARG, "src or dst is NULL");
+    if (dtype != PRTGS_BF16 && dtype != PRTGS_F16) return fail(PRTGS_ERR_INVALID_ARG, "pack dtype must be BF16 or F16");
+    return hip_status(launch_pack(count, src, dst, dtype, stream), "pack");
+}
+
+prtgs_status prtgs_relight(int32_t n, int32_t K, int32_t C, const void* transfer, prtgs_dtype t_dtype, int32_t B,
+                           const float* light, void* colour, prtgs_dtype out_dtype, hipStream_t stream)
+{
+    if (n < 0) return fail(PRTGS_ERR_INVALID_ARG, "n < 0");
+    if (K != 1 && K != 4 && K != 9 && K != 16) return fail(PRTGS_ERR_INVALID_ARG, "K = %d not in {1, 4, 9, 16}", K);
+    if (C != 1 && C != 3) return fail(PRTGS_ERR_INVALID_ARG, "C = %d not 1 or 3", C);
+    if (B < 1 || B > 256) return fail(PRTGS_ERR_INVALID_ARG, "B = %d outside [1, 256]", B);
+    if (t_dtype != PRTGS_F32 && t_dtype != PRTGS_BF16 && t_dtype != PRTGS_F16)
+        return fail(PRTGS_ERR_INVALID_ARG, "bad transfer dtype");
+    if (out_dtype != PRTGS_F32 && out_dtype != PRTGS_F16) return fail(PRTGS_ERR_INVALID_ARG, "colour dtype must be F32 or F16");
+    if (n == 0) return ok();
+    if (!transfer || !light || !colour) return fail(PRTGS_ERR_INVALID_ARG, "a relight pointer is NULL");
+    if ((int64_t)n * B * 3 > ((int64_t)1 << 40)) return fail(PRTGS_ERR_INVALID_ARG, "colour array too large");
+    return hip_status(launch_relight(n, K, C, transfer, t_dtype, B, light, colour, out_dtype, stream), "relight");
+}
+
+size_t prtgs_relight_backward_workspace_bytes(int32_t n, int32_t K, int32_t C, int32_t B)
+{
+    if (n < 0 || K < 1 || K > 16 || (C != 1 && C != 3) || B < 1 || B > 256) return 0;
+    return relight_backward_ws(n, K, C, B);
+}
+
+prtgs_status prtgs_relight_backward(int32_t n, int32_t K, int32_t C, const float* transfer, int32_t B,
+                                    const float* light, const float* d_colour, float* d_transfer, float* d_light,
+                                    void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (n < 0) return fail(PRTGS_ERR_INVALID_ARG, "n < 0");
+    if (K != 1 && K != 4 && K != 9 && K != 16) return fail(PRTGS_ERR_INVALID_ARG, "K = %d not in {1, 4, 9, 16}", K);
+    if (C != 1 && C != 3) return fail(PRTGS_ERR_INVALID_ARG, "C = %d not 1 or 3", C);
+    if (B < 1 || B > 256) return fail(PRTGS_ERR_INVALID_ARG, "B = %d outside [1, 256]", B);
+    if (!d_transfer && !d_light) return ok();
+    if (!light || !d_colour || (d_light && !transfer)) return fail(PRTGS_ERR_INVALID_ARG, "a relight pointer is NULL");
+    if (!ws || !aligned256(ws)) return fail(PRTGS_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
+    size_t need = relight_backward_ws(n, K, C, B);
+    if (ws_bytes < need) return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    return hip_status(launch_relight_backward(n, K, C, transfer, B, light, d_colour, d_transfer, d_light, ws, stream),
+                      "relight backward");
+}
+
+size_t prtgs_transfer_backward_workspace_bytes(const prtgs_transfer_desc* d, int32_t n)
+{
+    if (!d || n < 1 || check_desc(d) != PRTGS_OK) return 0;
+    TransferWs W = transfer_ws_layout(*d, n);
+    // + per-leaf scratch gradients: W (9), mu (3), opacity (1), normal (3)
+    return W.total + align256(sizeof(float) * 16 * (size_t)n);
+}
+
+prtgs_status prtgs_transfer_backward(const prtgs_gaussians* g, const void* bvh, const prtgs_transfer_desc* d,
+                                     const float* d_transfer, const prtgs_grads* grads, void* ws, size_t ws_bytes,
+                                     hipStream_t stream)
+{
+    prtgs_status st = check_desc(d);
+    if (st != PRTGS_OK) return st;
+    if (d->bounces != 0) return fail(PRTGS_ERR_UNSUPPORTED, "the adjoint covers the direct transfer only (bounces = 0)");
+    st = check_gaussians(g, false);
+    if (st != PRTGS_OK) return st;
+    if (!grads) return fail(PRTGS_ERR_INVALID_ARG, "grads struct is NULL");
+    if (!bvh || !ws || !d_transfer) return fail(PRTGS_ERR_INVALID_ARG, "bvh, workspace or d_transfer is NULL");
+    if (!aligned256(bvh) || !aligned256(ws)) return fail(PRTGS_ERR_INVALID_ARG, "bvh and workspace must be 256-byte aligned");
+    const int n = g->n;
+    size_t need = prtgs_transfer_backward_workspace_bytes(d, n);
+    if (ws_bytes < need) return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    if (!grads->d_means && !grads->d_quats && !grads->d_log_scales && !grads->d_opacity && !grads->d_normals) return ok();
+
+    TransferWs W = transfer_ws_layout(*d, n);
+    char* w = static_cast<char*>(ws);
+    unsigned* flags = reinterpret_cast<unsigned*>(w);
+    float* dirs = reinterpret_cast<float*>(w + W.dirs);
+    float* Y = reinterpret_cast<float*>(w + W.Y);
+    float* scratch = reinterpret_cast<float*>(w + W.total);
+    hipError_t e = fill_u32(flags, 0u, 1, stream);
+    if (e == hipSuccess)
+        e = launch_direction_table(d->num_dirs, d->seed, d->sh_bands, nullptr, nullptr, dirs, Y, stream);
+    if (e == hipSuccess) e = fill_u32(reinterpret_cast<uint32_t*>(scratch), 0u, 16 * (size_t)n, stream);
+    if (e != hipSuccess) return hip_status(e, "backward setup");
+
+    const BvhLayout L = bvh_layout(n);
+    const char* b = static_cast<const char*>(bvh);
+    BackwardArgs a;
+    a.fwd.nodes = reinterpret_cast<const Node*>(b + L.nodes);
+    a.fwd.prims = reinterpret_cast<const Prim*>(b + L.prims);
+    a.fwd.order = reinterpret_cast<const int32_t*>(b + L.order);
+    a.fwd.dirs = dirs;
+    a.fwd.Y = Y;
+    a.fwd.S = d->num_dirs;
+    a.fwd.K = d->sh_bands * d->sh_bands;
+    a.fwd.n = n;
+    a.fwd.first = 0;
+    a.fwd.count = n;
+    a.fwd.channels = 1;
+    a.fwd.hp = hit_params(*d);
+    a.fwd.transfer = nullptr;
+    a.fwd.vis = nullptr;
+    a.fwd.tdir_sorted = nullptr;
+    a.fwd.albedo = nullptr;
+    a.fwd.flags = flags;
+    a.d_transfer = d_transfer;
+    a.g_W = scratch;
+    a.g_mu = scratch + 9 * (size_t)n;
+    a.g_o = scratch + 12 * (size_t)n;
+    a.g_n = scratch + 13 * (size_t)n;
+    a.quats = g->quats;
+    a.log_scales = g->log_scales;
+    a.out = *grads;
+    return hip_status(launch_transfer_backward(a, stream), "transfer backward");
+}
+
+}  // extern "C"

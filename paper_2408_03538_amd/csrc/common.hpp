@@ -1,0 +1,149 @@
+// Shared device-side definitions of the PRTGS HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "prtgs.h"
+
+namespace prtgs {
+
+constexpr int kWave = 64;                 // CDNA wavefront width
+constexpr float kBoxSigma = 3.0f;         // BVH boxes enclose the 3-sigma ellipsoid
+constexpr size_t kFlagBytes = 256;        // flag word + padding at the head of a workspace
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Internal BVH node: the boxes of both children and their references.  A
+// reference r >= 0 is an internal node, r < 0 the leaf ~r (a leaf rank).
+// a = (L.lo.x, L.lo.y, L.lo.z, L.hi.x)  b = (L.hi.y, L.hi.z, R.lo.x, R.lo.y)
+// c = (R.lo.z, R.hi.x, R.hi.y, R.hi.z)  d = (left ref, right ref, -, -)
+struct __align__(16) Node {
+    float4 a, b, c;
+    int4 d;
+};
+
+// Ray-test record of one Gaussian, in leaf order: centre and opacity, then
+// the rows of the whitening matrix W = diag(1/s) R^T (so that W^T W is the
+// inverse covariance of Eq. 2) with the normal's components in .w.
+struct __align__(16) Prim {
+    float4 mo;   // mu.x, mu.y, mu.z, opacity
+    float4 w0;   // W row 0, normal.x
+    float4 w1;   // W row 1, normal.y
+    float4 w2;   // W row 2, normal.z
+};
+
+struct BvhHeader {
+    int32_t n;
+    int32_t max_depth;
+    int32_t pad0, pad1;
+    float lo[4];
+    float hi[4];
+};
+
+struct BvhLayout {
+    size_t nodes, prims, order, total;
+};
+
+inline BvhLayout bvh_layout(int n)
+{
+    BvhLayout L;
+    size_t off = align256(sizeof(BvhHeader));
+    L.nodes = off;
+    off += align256(sizeof(Node) * (size_t)(n > 1 ? n - 1 : 1));
+    L.prims = off;
+    off += align256(sizeof(Prim) * (size_t)n);
+    L.order = off;
+    off += align256(sizeof(int32_t) * (size_t)n);
+    L.total = off;
+    return L;
+}
+
+// Cutoffs of the hit test, as used on the device.
+struct HitParams {
+    float cut2;       // sigma_cut^2
+    float t_min;
+    float T_eps;
+    float alpha_min;
+    float alpha_max;
+};
+
+// Load at a wave-uniform address through the constant address space, so the
+// compiler issues a scalar (s_load) instead of a per-lane vector load.  Only
+// for memory that no kernel writes while the loading kernel runs.
+template <class T>
+__device__ inline T uniform_load(const T* p, size_t idx)
+{
+    static_assert(sizeof(T) % 4 == 0, "whole dwords only");
+    typedef const uint32_t __attribute__((address_space(4)))* cptr;
+    const cptr src = (cptr)(p + idx);
+    T out;
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+    for (size_t i = 0; i < sizeof(T) / 4; ++i) dst[i] = src[i];
+    return out;
+}
+
+__device__ inline void raise_flag(unsigned* flags, unsigned bit)
+{
+    if (flags) atomicOr(flags, bit);
+}
+
+__device__ inline bool finite3(float a, float b, float c)
+{
+    return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+// Fill kernel used instead of hipMemsetAsync, so that callers may capture
+// the library's work in a graph.
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t count);
+hipError_t fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t stream);
+
+// ------------------------------------------------------------------------
+// host-side entry points of the individual translation units
+// ------------------------------------------------------------------------
+hipError_t launch_direction_table(int S, uint64_t seed, int bands, double* d64, double* y64, float* d32,
+                                  float* y32, hipStream_t stream);
+hipError_t launch_build_bvh(const prtgs_gaussians& g, void* bvh, void* ws, unsigned* flags, hipStream_t stream);
+size_t build_workspace_bytes(int n);
+hipError_t launch_leaf_order(const void* bvh, int n, int32_t* order, hipStream_t stream);
+
+struct TransferArgs {
+    const Node* nodes;
+    const Prim* prims;
+    const int32_t* order;
+    const float* dirs;      // [S][3]
+    const float* Y;         // [S][K]
+    int S, K, n, first, count, channels;
+    HitParams hp;
+    float* transfer;        // [n][C][K]
+    float* vis;             // [n][S] or null
+    float* tdir_sorted;     // [n][K] leaf order, or null
+    const float* albedo;    // [n][3] original order (bounce)
+    unsigned* flags;
+};
+hipError_t launch_transfer_direct(const TransferArgs& a, hipStream_t stream);
+hipError_t launch_transfer_bounce(const TransferArgs& a, hipStream_t stream);
+
+struct BackwardArgs {
+    TransferArgs fwd;
+    const float* d_transfer;  // [n][1][K]
+    float* g_W;               // [n][9] scratch: dLoss/dW, leaf order
+    float* g_mu;              // [n][3] scratch, leaf order
+    float* g_o;               // [n]    scratch, leaf order
+    float* g_n;               // [n][3] scratch, leaf order
+    const float* quats;       // original order inputs
+    const float* log_scales;
+    prtgs_grads out;
+};
+hipError_t launch_transfer_backward(const BackwardArgs& a, hipStream_t stream);
+
+hipError_t launch_pack(int64_t count, const float* src, void* dst, prtgs_dtype dtype, hipStream_t stream);
+hipError_t launch_relight(int n, int K, int C, const void* T, prtgs_dtype tdt, int B, const float* L,
+                          void* out, prtgs_dtype odt, hipStream_t stream);
+hipError_t launch_relight_backward(int n, int K, int C, const float* T, int B, const float* L,
+                                   const float* dC, float* dT, float* dL, void* ws, hipStream_t stream);
+size_t relight_backward_ws(int n, int K, int C, int B);
+
+}  // namespace prtgs

@@ -1,0 +1,428 @@
+// Relighting (Eq. 14 and, for an RGB transfer, Eq. 41 per channel): per
+// splat and light environment the colour is the dot product of the splat's
+// transfer vector with the light's SH coefficients,
+//   colour[i][b][c] = sum_k T[i][c'][k] L[b][c][k],  c' = (C == 3 ? c : 0).
+// With 16-bit transfers this is a batched GEMM on MFMA; the FP32 path uses
+// VALU FMAs.  Both are bound by HBM bandwidth (colour writes dominate).
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "common.hpp"
+
+namespace prtgs {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ pack
+
+__global__ void pack_kernel(int64_t count, const float* __restrict__ src, void* __restrict__ dst, int dtype)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (dtype == PRTGS_BF16) {
+        __hip_bfloat16* d = static_cast<__hip_bfloat16*>(dst);
+        for (; i < count; i += stride) d[i] = __float2bfloat16(src[i]);
+    } else {
+        __half* d = static_cast<__half*>(dst);
+        for (; i < count; i += stride) d[i] = __float2half(src[i]);
+    }
+}
+
+// ------------------------------------------------------------------ FP32 path
+// A block takes 64 splats: their transfer rows are staged in LDS and every
+// thread owns up to MC output columns (b, c), keeping L[b][c][:] in registers.
+
+constexpr int kRowsF32 = 64;
+constexpr int kThreadsF32 = 256;
+
+template <int K, int C, int MC, bool OUT16>
+__global__ __launch_bounds__(kThreadsF32) void relight_f32_kernel(int n, const float* __restrict__ T, int B,
+                                                                  const float* __restrict__ L, void* __restrict__ out)
+{
+    __shared__ float rows[kRowsF32 * C * K];
+    const int cols = 3 * B;
+    float lreg[MC][K];
+    int chan[MC];
+#pragma unroll
+    for (int m = 0; m < MC; ++m) {
+        int col = threadIdx.x + m * kThreadsF32;
+        int cc = col < cols ? col : 0;
+        chan[m] = (C == 3) ? (cc % 3) : 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) lreg[m][k] = col < cols ? L[(size_t)cc * K + k] : 0.0f;
+    }
+    for (int64_t base = (int64_t)blockIdx.x * kRowsF32; base < n; base += (int64_t)gridDim.x * kRowsF32) {
+        const int nrows = (int)((n - base) < kRowsF32 ? (n - base) : kRowsF32);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nrows * C * K; e += kThreadsF32) rows[e] = T[base * C * K + e];
+        __syncthreads();
+        for (int r = 0; r < nrows; ++r) {
+#pragma unroll
+            for (int m = 0; m < MC; ++m) {
+                int col = threadIdx.x + m * kThreadsF32;
+                if (col < cols) {
+                    const float* tr = rows + (r * C + chan[m]) * K;
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) acc = fmaf(tr[k], lreg[m][k], acc);
+                    size_t o = (size_t)(base + r) * cols + col;
+                    if (OUT16) static_cast<__half*>(out)[o] = __float2half(acc);
+                    else static_cast<float*>(out)[o] = acc;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ MFMA path
+// GEMM of 16-splat row tiles against column tiles of 16 outputs (b, c) with
+// v_mfma_f32_16x16x32_{bf16,f16}.  The 32-deep contraction of one MFMA is
+// [T_c' | T_c'] . [L_hi ; L_lo] for channel c', where L_hi is the light
+// rounded to 16 bits and L_lo the rounded remainder, so the light enters at
+// ~FP32 precision; columns of other channels get zeros (C == 3 needs C such
+// steps).  Lane l holds A[l % 16][8 (l / 16) + 0..7], B[8 (l / 16) + 0..7][l % 16]
+// and D[4 (l / 16) + 0..3][l % 16].  Each of the 4 waves of a block owns MT
+// column tiles, whose B fragments stay in registers; the 16 x 3B output tile
+// of a row tile is contiguous in memory and is staged in LDS for full-width
+// stores.
+
+constexpr int kWavesMfma = 4;
+
+template <bool BF>
+struct Frag;
+template <>
+struct Frag<true> {
+    using vec = bf16x8;
+    using elem = __bf16;
+    static __device__ inline f32x4 mma(vec a, vec b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+    static __device__ inline elem from_float(float x) { return (elem)x; }
+};
+template <>
+struct Frag<false> {
+    using vec = f16x8;
+    using elem = _Float16;
+    static __device__ inline f32x4 mma(vec a, vec b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+    static __device__ inline elem from_float(float x) { return (elem)x; }
+};
+
+template <int K, int C, int MT, bool BF, bool OUT16>
+__global__ __launch_bounds__(kWavesMfma * kWave) void relight_mfma_kernel(int n, const void* __restrict__ Tv, int B,
+                                                                          const float* __restrict__ L,
+                                                                          void* __restrict__ out)
+{
+    using F = Frag<BF>;
+    using vec = typename F::vec;
+    using elem = typename F::elem;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const elem* T = static_cast<const elem*>(Tv);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int cols = 3 * B;
+    const int ntiles = (cols + 15) / 16;
+    const int g = lane / 16;   // k group of the lane's A/B fragment
+    const int li = lane % 16;  // row (A) / column (B, D) of the lane
+
+    // B fragments of this wave's column tiles, for every channel step
+    vec bfrag[MT][C];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        int tile = wave + m * kWavesMfma;
+        int col = tile * 16 + li;
+        bool cvalid = tile < ntiles && col < cols;
+        int ch = cvalid ? col % 3 : 0;
+#pragma unroll
+        for (int st = 0; st < C; ++st) {
+            vec v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                int k = 8 * g + e;          // 0..31
+                int kk = k & 15;
+                bool lo = k >= 16;
+                float x = 0.0f;
+                if (cvalid && kk < K && (C == 1 || ch == st)) {
+                    float full = L[(size_t)col * K + kk];
+                    elem hi = F::from_float(full);
+                    x = lo ? (full - (float)hi) : full;
+                }
+                v[e] = F::from_float(x);
+            }
+            bfrag[m][st] = v;
+        }
+    }
+
+    const size_t row_elems = (size_t)cols;
+    for (int64_t base = (int64_t)blockIdx.x * 16; base < n; base += (int64_t)gridDim.x * 16) {
+        const int64_t row = base + li;
+        const bool rvalid = row < n;
+        vec afrag[C];
+#pragma unroll
+        for (int st = 0; st < C; ++st) {
+            if (K == 16 && rvalid) {
+                const elem* src = T + ((size_t)row * C + st) * 16 + 8 * (g & 1);
+                afrag[st] = *reinterpret_cast<const vec*>(src);
+            } else {
+                vec v;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    int kk = (8 * g + e) & 15;
+                    v[e] = (rvalid && kk < K) ? T[((size_t)row * C + st) * K + kk] : F::from_float(0.0f);
+                }
+                afrag[st] = v;
+            }
+        }
+        const int nrows = (int)((n - base) < 16 ? (n - base) : 16);
+        __syncthreads();   // previous tile's stores have read the staging area
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            int tile = wave + m * kWavesMfma;
+            if (tile < ntiles) {
+                f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int st = 0; st < C; ++st) acc = F::mma(afrag[st], bfrag[m][st], acc);
+                int col = tile * 16 + li;
+                if (col < cols) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        int r = 4 * g + v;
+                        if (OUT16) reinterpret_cast<__half*>(smem)[r * cols + col] = __float2half(acc[v]);
+                        else reinterpret_cast<float*>(smem)[r * cols + col] = acc[v];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // the tile's rows are one contiguous run of nrows * cols values
+        const size_t total = (size_t)nrows * row_elems;
+        const size_t obase = (size_t)base * row_elems;
+        if (OUT16) {
+            const size_t nvec = total / 8;
+            const uint4* s4 = reinterpret_cast<const uint4*>(smem);
+            __half* o = static_cast<__half*>(out) + obase;
+            if ((reinterpret_cast<uintptr_t>(o) & 15) == 0) {
+                for (size_t e = threadIdx.x; e < nvec; e += blockDim.x) reinterpret_cast<uint4*>(o)[e] = s4[e];
+                for (size_t e = nvec * 8 + threadIdx.x; e < total; e += blockDim.x)
+                    o[e] = reinterpret_cast<const __half*>(smem)[e];
+            } else {
+                for (size_t e = threadIdx.x; e < total; e += blockDim.x) o[e] = reinterpret_cast<const __half*>(smem)[e];
+            }
+        } else {
+            const size_t nvec = total / 4;
+            const float4* s4 = reinterpret_cast<const float4*>(smem);
+            float* o = static_cast<float*>(out) + obase;
+            if ((reinterpret_cast<uintptr_t>(o) & 15) == 0) {
+                for (size_t e = threadIdx.x; e < nvec; e += blockDim.x) reinterpret_cast<float4*>(o)[e] = s4[e];
+                for (size_t e = nvec * 4 + threadIdx.x; e < total; e += blockDim.x)
+                    o[e] = reinterpret_cast<const float*>(smem)[e];
+            } else {
+                for (size_t e = threadIdx.x; e < total; e += blockDim.x) o[e] = reinterpret_cast<const float*>(smem)[e];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ backward
+
+constexpr int kBwdRows = 1024;
+
+// d_transfer[i][c'][k] = sum over (b, c -> c') of d_colour[i][b][c] L[b][c][k]
+template <int K, int C>
+__global__ void relight_dT_kernel(int n, int B, const float* __restrict__ L, const float* __restrict__ dC,
+                                  float* __restrict__ dT)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * C * K) return;
+    int k = (int)(idx % K);
+    int cp = (int)((idx / K) % C);
+    int64_t i = idx / ((int64_t)C * K);
+    float acc = 0.0f;
+    for (int b = 0; b < B; ++b) {
+        if (C == 3) {
+            acc = fmaf(dC[((size_t)i * B + b) * 3 + cp], L[((size_t)b * 3 + cp) * K + k], acc);
+        } else {
+            for (int c = 0; c < 3; ++c) acc = fmaf(dC[((size_t)i * B + b) * 3 + c], L[((size_t)b * 3 + c) * K + k], acc);
+        }
+    }
+    dT[idx] = acc;
+}
+
+// partial[blk][b][c][k] = sum over the block's rows of d_colour[i][b][c] T[i][c'][k]
+template <int K, int C>
+__global__ void relight_dL_partial_kernel(int n, int B, const float* __restrict__ T, const float* __restrict__ dC,
+                                          float* __restrict__ partial)
+{
+    const int outs = B * 3 * K;
+    const int64_t r0 = (int64_t)blockIdx.x * kBwdRows;
+    const int64_t r1 = r0 + kBwdRows < n ? r0 + kBwdRows : n;
+    for (int o = threadIdx.x; o < outs; o += blockDim.x) {
+        int k = o % K;
+        int c = (o / K) % 3;
+        int b = o / (3 * K);
+        int cp = C == 3 ? c : 0;
+        float sum = 0.0f, comp = 0.0f;
+        for (int64_t i = r0; i < r1; ++i) {
+            float x = dC[((size_t)i * B + b) * 3 + c] * T[((size_t)i * C + cp) * K + k];
+            float y = x - comp;
+            float t = sum + y;
+            comp = (t - sum) - y;
+            sum = t;
+        }
+        partial[(size_t)blockIdx.x * outs + o] = sum;
+    }
+}
+
+__global__ void relight_dL_final_kernel(int nparts, int outs, const float* __restrict__ partial, float* __restrict__ dL)
+{
+    int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= outs) return;
+    float sum = 0.0f, comp = 0.0f;
+    for (int p = 0; p < nparts; ++p) {
+        float y = partial[(size_t)p * outs + o] - comp;
+        float t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+    }
+    dL[o] = sum;
+}
+
+// ------------------------------------------------------------------ dispatch
+
+template <int K, int C, int MC>
+hipError_t f32_dispatch_out(int n, const float* T, int B, const float* L, void* out, bool out16, hipStream_t stream)
+{
+    int blocks = (int)((n + kRowsF32 - 1) / kRowsF32);
+    if (blocks > 65536) blocks = 65536;
+    if (out16)
+        hipLaunchKernelGGL((relight_f32_kernel<K, C, MC, true>), dim3(blocks), dim3(kThreadsF32), 0, stream, n, T, B, L, out);
+    else
+        hipLaunchKernelGGL((relight_f32_kernel<K, C, MC, false>), dim3(blocks), dim3(kThreadsF32), 0, stream, n, T, B, L, out);
+    return hipGetLastError();
+}
+
+template <int K, int C>
+hipError_t f32_dispatch(int n, const float* T, int B, const float* L, void* out, bool out16, hipStream_t stream)
+{
+    int mc = (3 * B + kThreadsF32 - 1) / kThreadsF32;
+    if (mc <= 1) return f32_dispatch_out<K, C, 1>(n, T, B, L, out, out16, stream);
+    if (mc <= 2) return f32_dispatch_out<K, C, 2>(n, T, B, L, out, out16, stream);
+    return f32_dispatch_out<K, C, 3>(n, T, B, L, out, out16, stream);
+}
+
+template <int K, int C, int MT, bool BF>
+hipError_t mfma_dispatch_out(int n, const void* T, int B, const float* L, void* out, bool out16, hipStream_t stream)
+{
+    int blocks = (int)((n + 15) / 16);
+    if (blocks > 8192) blocks = 8192;
+    size_t shmem = (size_t)16 * 3 * B * (out16 ? 2 : 4);
+    if (out16)
+        hipLaunchKernelGGL((relight_mfma_kernel<K, C, MT, BF, true>), dim3(blocks), dim3(kWavesMfma * kWave), shmem,
+                           stream, n, T, B, L, out);
+    else
+        hipLaunchKernelGGL((relight_mfma_kernel<K, C, MT, BF, false>), dim3(blocks), dim3(kWavesMfma * kWave), shmem,
+                           stream, n, T, B, L, out);
+    return hipGetLastError();
+}
+
+template <int K, int C, bool BF>
+hipError_t mfma_dispatch(int n, const void* T, int B, const float* L, void* out, bool out16, hipStream_t stream)
+{
+    int ntiles = (3 * B + 15) / 16;
+    int mt = (ntiles + kWavesMfma - 1) / kWavesMfma;
+    if (mt <= 1) return mfma_dispatch_out<K, C, 1, BF>(n, T, B, L, out, out16, stream);
+    if (mt <= 2) return mfma_dispatch_out<K, C, 2, BF>(n, T, B, L, out, out16, stream);
+    if (mt <= 3) return mfma_dispatch_out<K, C, 3, BF>(n, T, B, L, out, out16, stream);
+    if (mt <= 6) return mfma_dispatch_out<K, C, 6, BF>(n, T, B, L, out, out16, stream);
+    return mfma_dispatch_out<K, C, 12, BF>(n, T, B, L, out, out16, stream);
+}
+
+template <int K, int C>
+hipError_t relight_kc(int n, const void* T, prtgs_dtype tdt, int B, const float* L, void* out, prtgs_dtype odt,
+                      hipStream_t stream)
+{
+    bool out16 = odt == PRTGS_F16;
+    if (tdt == PRTGS_F32) return f32_dispatch<K, C>(n, static_cast<const float*>(T), B, L, out, out16, stream);
+    if (tdt == PRTGS_BF16) return mfma_dispatch<K, C, true>(n, T, B, L, out, out16, stream);
+    return mfma_dispatch<K, C, false>(n, T, B, L, out, out16, stream);
+}
+
+template <int K>
+hipError_t relight_k(int n, int C, const void* T, prtgs_dtype tdt, int B, const float* L, void* out, prtgs_dtype odt,
+                     hipStream_t stream)
+{
+    if (C == 3) return relight_kc<K, 3>(n, T, tdt, B, L, out, odt, stream);
+    return relight_kc<K, 1>(n, T, tdt, B, L, out, odt, stream);
+}
+
+template <int K, int C>
+hipError_t relight_bwd_kc(int n, const float* T, int B, const float* L, const float* dC, float* dT, float* dL,
+                          void* ws, hipStream_t stream)
+{
+    if (dT && n > 0) {
+        int64_t total = (int64_t)n * C * K;
+        int blocks = (int)((total + 255) / 256);
+        hipLaunchKernelGGL((relight_dT_kernel<K, C>), dim3(blocks), dim3(256), 0, stream, n, B, L, dC, dT);
+    }
+    if (dL) {
+        int outs = B * 3 * K;
+        int nparts = (n + kBwdRows - 1) / kBwdRows;
+        float* partial = reinterpret_cast<float*>(static_cast<char*>(ws) + kFlagBytes);
+        if (nparts > 0)
+            hipLaunchKernelGGL((relight_dL_partial_kernel<K, C>), dim3(nparts), dim3(256), 0, stream, n, B, T, dC, partial);
+        hipLaunchKernelGGL(relight_dL_final_kernel, dim3((outs + 255) / 256), dim3(256), 0, stream, nparts, outs, partial, dL);
+    }
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t relight_bwd_k(int n, int C, const float* T, int B, const float* L, const float* dC, float* dT, float* dL,
+                         void* ws, hipStream_t stream)
+{
+    if (C == 3) return relight_bwd_kc<K, 3>(n, T, B, L, dC, dT, dL, ws, stream);
+    return relight_bwd_kc<K, 1>(n, T, B, L, dC, dT, dL, ws, stream);
+}
+
+}  // namespace
+
+hipError_t launch_pack(int64_t count, const float* src, void* dst, prtgs_dtype dtype, hipStream_t stream)
+{
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, count, src, dst, (int)dtype);
+    return hipGetLastError();
+}
+
+hipError_t launch_relight(int n, int K, int C, const void* T, prtgs_dtype tdt, int B, const float* L, void* out,
+                          prtgs_dtype odt, hipStream_t stream)
+{
+    switch (K) {
+        case 1: return relight_k<1>(n, C, T, tdt, B, L, out, odt, stream);
+        case 4: return relight_k<4>(n, C, T, tdt, B, L, out, odt, stream);
+        case 9: return relight_k<9>(n, C, T, tdt, B, L, out, odt, stream);
+        case 16: return relight_k<16>(n, C, T, tdt, B, L, out, odt, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t relight_backward_ws(int n, int K, int C, int B)
+{
+    (void)C;
+    size_t nparts = (size_t)((n + kBwdRows - 1) / kBwdRows);
+    return kFlagBytes + align256(sizeof(float) * nparts * (size_t)B * 3 * (size_t)K);
+}
+
+hipError_t launch_relight_backward(int n, int K, int C, const float* T, int B, const float* L, const float* dC,
+                                   float* dT, float* dL, void* ws, hipStream_t stream)
+{
+    switch (K) {
+        case 1: return relight_bwd_k<1>(n, C, T, B, L, dC, dT, dL, ws, stream);
+        case 4: return relight_bwd_k<4>(n, C, T, B, L, dC, dT, dL, ws, stream);
+        case 9: return relight_bwd_k<9>(n, C, T, B, L, dC, dT, dL, ws, stream);
+        case 16: return relight_bwd_k<16>(n, C, T, B, L, dC, dT, dL, ws, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace prtgs

@@ -1,0 +1,148 @@
+// Direction / SH-basis table: S stratified equal-area directions and the
+// real orthonormal spherical harmonics at them (SH projection, Eq. 8-11),
+// generated in FP64 on the device.
+#include "common.hpp"
+
+namespace prtgs {
+
+namespace {
+
+// SplitMix64 (Steele, Lea & Flood 2014): output `idx` of the stream seeded
+// with `seed` is the finaliser applied to seed + (idx + 1) * golden gamma.
+__device__ inline uint64_t mix64(uint64_t seed, uint64_t idx)
+{
+    uint64_t z = seed + (idx + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline double unit53(uint64_t seed, uint64_t idx)
+{
+    return (double)(mix64(seed, idx) >> 11) * 0x1.0p-53;
+}
+
+// Real SH through solid-harmonic polynomials: with r^m cos(m phi) and
+// r^m sin(m phi) built as the real and imaginary parts of (x + i y)^m, and
+// the associated Legendre function divided by (1 - z^2)^(m/2) (a polynomial
+// in z, Condon-Shortley phase included) from its recurrence in l, the basis is
+//   Y_l^{+m} = sqrt2 K_l^m Pbar_l^m(z) Re(x+iy)^m,   Y_l^{-m} = sqrt2 K_l^m Pbar_l^m(z) Im(x+iy)^m,
+//   Y_l^0 = K_l^0 Pbar_l^0(z),   K_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!).
+constexpr int kMaxBands = 8;
+
+__device__ void real_sh(int bands, double x, double y, double z, double* out)
+{
+    double re = 1.0, im = 0.0;          // (x + i y)^m
+    double pmm = 1.0;                   // Pbar_m^m = (-1)^m (2m-1)!!
+    for (int m = 0; m < bands; ++m) {
+        if (m > 0) {
+            double nre = re * x - im * y;
+            im = re * y + im * x;
+            re = nre;
+            pmm *= -(2.0 * m - 1.0);
+        }
+        double p_lm2 = 0.0, p_lm1 = pmm;
+        for (int l = m; l < bands; ++l) {
+            double p;
+            if (l == m) p = pmm;
+            else if (l == m + 1) p = z * (2.0 * m + 1.0) * pmm;
+            else p = ((2.0 * l - 1.0) * z * p_lm1 - (l + m - 1.0) * p_lm2) / (double)(l - m);
+            if (l > m) {
+                p_lm2 = p_lm1;
+                p_lm1 = p;
+            }
+            double fr = 1.0;            // (l-m)! / (l+m)!
+            for (int f = l - m + 1; f <= l + m; ++f) fr /= (double)f;
+            double K = sqrt((2.0 * l + 1.0) * fr / (4.0 * 3.14159265358979323846));
+            int base = l * l + l;
+            if (m == 0) {
+                out[base] = K * p;
+            } else {
+                out[base + m] = 1.41421356237309504880 * K * p * re;
+                out[base - m] = 1.41421356237309504880 * K * p * im;
+            }
+        }
+    }
+}
+
+__global__ void direction_table_kernel(int S, int nu, int nv, uint64_t seed, int bands, double* d64, double* y64,
+                                       float* d32, float* y32)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    int a = s / nv, b = s - a * nv;
+    double xi = unit53(seed, 2ull * (uint64_t)s);
+    double eta = unit53(seed, 2ull * (uint64_t)s + 1ull);
+    double z = 1.0 - 2.0 * ((double)a + xi) / (double)nu;
+    double phi = 2.0 * 3.14159265358979323846 * ((double)b + eta) / (double)nv;
+    double r = sqrt(fmax(0.0, 1.0 - z * z));
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    float fx = (float)(r * cp), fy = (float)(r * sp), fz = (float)z;
+    if (d32) {
+        d32[3 * s + 0] = fx;
+        d32[3 * s + 1] = fy;
+        d32[3 * s + 2] = fz;
+    }
+    if (d64) {
+        d64[3 * s + 0] = (double)fx;
+        d64[3 * s + 1] = (double)fy;
+        d64[3 * s + 2] = (double)fz;
+    }
+    // the basis is evaluated at the FP32 direction, renormalised in FP64
+    double ux = fx, uy = fy, uz = fz;
+    double len = sqrt(ux * ux + uy * uy + uz * uz);
+    ux /= len;
+    uy /= len;
+    uz /= len;
+    double Y[kMaxBands * kMaxBands];
+    real_sh(bands, ux, uy, uz, Y);
+    int K = bands * bands;
+    for (int k = 0; k < K; ++k) {
+        if (y64) y64[(size_t)s * K + k] = Y[k];
+        if (y32) y32[(size_t)s * K + k] = (float)Y[k];
+    }
+}
+
+}  // namespace
+
+void stratified_grid(int S, int* nu, int* nv)
+{
+    int r = 1;
+    while ((r + 1) * (r + 1) <= S) ++r;
+    int u = 1;
+    for (int d = 1; d <= r; ++d)
+        if (S % d == 0) u = d;
+    *nu = u;
+    *nv = S / u;
+}
+
+hipError_t launch_direction_table(int S, uint64_t seed, int bands, double* d64, double* y64, float* d32,
+                                  float* y32, hipStream_t stream)
+{
+    int nu, nv;
+    stratified_grid(S, &nu, &nv);
+    int threads = 64;
+    int blocks = (S + threads - 1) / threads;
+    hipLaunchKernelGGL(direction_table_kernel, dim3(blocks), dim3(threads), 0, stream, S, nu, nv, seed, bands, d64,
+                       y64, d32, y32);
+    return hipGetLastError();
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t count)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) p[i] = v;
+}
+
+hipError_t fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t stream)
+{
+    if (count == 0) return hipSuccess;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, v, count);
+    return hipGetLastError();
+}
+
+}  // namespace prtgs

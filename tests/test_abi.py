@@ -1,0 +1,108 @@
+"""The C ABI library: it loads, exports every declared symbol, and rejects bad
+arguments on the host before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "prtgs.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(prtgs_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2408_03538_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libprtgs.so is not built (python -m paper_2408_03538_amd.build)")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_the_header():
+    from paper_2408_03538_amd import _lib
+    assert set(_declared()) == set(_lib.SIGNATURES)
+
+
+def test_abi_version(lib):
+    assert lib.prtgs_abi_version() == 1
+
+
+def test_size_queries(lib):
+    from paper_2408_03538_amd import _lib
+    assert lib.prtgs_bvh_bytes(0) == 0
+    small, big = lib.prtgs_bvh_bytes(1000), lib.prtgs_bvh_bytes(1_000_000)
+    assert small >= 1000 * 64 + 999 * 64 and big > 100 * small
+    assert lib.prtgs_build_workspace_bytes(1000) > 0
+    d = _lib.TransferDesc(64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99)
+    assert lib.prtgs_transfer_workspace_bytes(ctypes.byref(d), 1000) > 64 * 4 * 12
+    bad = _lib.TransferDesc(64, 9, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99)
+    assert lib.prtgs_transfer_workspace_bytes(ctypes.byref(bad), 1000) == 0
+    assert lib.prtgs_relight_backward_workspace_bytes(100, 16, 3, 64) > 0
+
+
+@pytest.mark.parametrize("desc,status", [
+    ((64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99), 1),     # NULL pointers in the scene
+    ((0, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99), 1),      # no directions
+    ((64, 5, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99), 1),     # too many bands
+    ((64, 3, 0, 2, 3.0, 0.0, 1e-4, 0.0, 0.99), 1),     # two bounces
+    ((64, 3, 0, 0, 4.0, 0.0, 1e-4, 0.0, 0.99), 1),     # cut-off beyond the 3-sigma boxes
+    ((64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 1.0), 1),      # alpha_max = 1
+])
+def test_transfer_validation(lib, desc, status):
+    from paper_2408_03538_amd import _lib
+    g = _lib.Gaussians(10, None, None, None, None, None, None)
+    d = _lib.TransferDesc(*desc)
+    st = lib.prtgs_precompute_transfer(ctypes.byref(g), None, ctypes.byref(d), 0, 10, None, None, None, 0, None)
+    assert st == status
+    assert lib.prtgs_last_error()
+
+
+def test_build_validation(lib):
+    from paper_2408_03538_amd import _lib
+    assert lib.prtgs_build_bvh(None, None, 0, None, 0, None) == 1
+    g = _lib.Gaussians(0, 256, 256, 256, 256, 256, None)
+    assert lib.prtgs_build_bvh(ctypes.byref(g), 256, 1 << 20, 256, 1 << 20, None) == 1
+    g = _lib.Gaussians(100, 256, 256, 256, 256, 256, None)
+    assert lib.prtgs_build_bvh(ctypes.byref(g), 256, 16, 256, 1 << 20, None) == 2   # BVH buffer too small
+    assert lib.prtgs_build_bvh(ctypes.byref(g), 257, 1 << 20, 256, 1 << 20, None) == 1  # misaligned
+    assert b"aligned" in lib.prtgs_last_error()
+
+
+def test_relight_validation(lib):
+    assert lib.prtgs_relight(10, 5, 1, 256, 0, 4, 256, 256, 0, None) == 1     # K = 5
+    assert lib.prtgs_relight(10, 16, 2, 256, 0, 4, 256, 256, 0, None) == 1    # C = 2
+    assert lib.prtgs_relight(10, 16, 3, 256, 0, 0, 256, 256, 0, None) == 1    # B = 0
+    assert lib.prtgs_relight(10, 16, 3, 256, 0, 4, 256, 256, 1, None) == 1    # bf16 output
+    assert lib.prtgs_relight(0, 16, 3, None, 0, 4, None, None, 0, None) == 0  # nothing to do
+    assert lib.prtgs_pack(10, None, None, 1, None) == 1
+    assert lib.prtgs_pack(10, 256, 256, 0, None) == 1                         # F32 is not a packed type
+
+
+def test_backward_rejects_bounce(lib):
+    from paper_2408_03538_amd import _lib
+    g = _lib.Gaussians(10, 256, 256, 256, 256, 256, 256)
+    d = _lib.TransferDesc(64, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99)
+    gr = _lib.Grads(None, None, None, None, None)
+    st = lib.prtgs_transfer_backward(ctypes.byref(g), 256, ctypes.byref(d), 256, ctypes.byref(gr), 256, 1 << 30, None)
+    assert st == 3
+
+
+def test_bounce_needs_whole_range(lib):
+    from paper_2408_03538_amd import _lib
+    g = _lib.Gaussians(10, 256, 256, 256, 256, 256, 256)
+    d = _lib.TransferDesc(64, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99)
+    st = lib.prtgs_precompute_transfer(ctypes.byref(g), 256, ctypes.byref(d), 2, 5, 256, None, 256, 1 << 30, None)
+    assert st == 1

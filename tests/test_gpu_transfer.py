@@ -1,0 +1,191 @@
+"""GPU parity of the direction table, the BVH and the transfer precompute
+against the CPU FP64 oracle (same seeded inputs, same directions/cut-offs)."""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen
+from helpers import as_f32, assert_transfer_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def prt():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2408_03538_amd as p
+    return p
+
+
+def _run(prt, scene64, params, want_vis=False):
+    sc = prt.Scene.from_arrays(scene64)
+    bvh = prt.build_bvh(sc, check=True)
+    res = prt.precompute_transfer(sc, bvh, params, want_vis=want_vis, check=True)
+    return sc, bvh, res
+
+
+# ---------------------------------------------------------------------------
+# direction table
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("S,seed,bands", [(64, 0, 3), (256, 0, 4), (512, 0, 4), (12, 7, 2), (1, 3, 1)])
+def test_direction_table(prt, oracle_mod, S, seed, bands):
+    d64, y64, d32, y32 = [t.cpu().numpy() for t in prt.direction_table(S, seed, bands)]
+    ref_d, ref_y = oracle_mod.tables(S, seed, bands)
+    same = (d32.astype(np.float64) == ref_d).all(axis=1)
+    assert same.mean() >= 0.99                       # FP32-rounded FP64 values; rare 1-ulp ties
+    assert np.abs(d32.astype(np.float64) - ref_d).max() < 2.5e-7
+    assert np.array_equal(d64, d32.astype(np.float64))
+    assert np.abs(y64 - ref_y)[same].max() < 1e-13
+    assert np.abs(y32.astype(np.float64) - ref_y).max() < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# BVH structure
+# ---------------------------------------------------------------------------
+
+def _parse_bvh(buf, n):
+    """Header, nodes, prims and leaf order from the documented buffer layout."""
+    def a256(x):
+        return (x + 255) // 256 * 256
+    raw = buf.cpu().numpy()
+    off_nodes = 256
+    off_prims = off_nodes + a256(64 * max(n - 1, 1))
+    off_order = off_prims + a256(64 * n)
+    nodes_f = raw[off_nodes:off_nodes + 64 * max(n - 1, 1)].view(np.float32).reshape(-1, 16)
+    nodes_i = raw[off_nodes:off_nodes + 64 * max(n - 1, 1)].view(np.int32).reshape(-1, 16)
+    prims = raw[off_prims:off_prims + 64 * n].view(np.float32).reshape(n, 16)
+    order = raw[off_order:off_order + 4 * n].view(np.int32)
+    hdr = raw[:48].view(np.int32)
+    return hdr, nodes_f, nodes_i, prims, order
+
+
+@pytest.mark.parametrize("gen,n", [("cloud", 1000), ("surface", 5000), ("cloud", 2), ("surface", 777)])
+def test_bvh_structure(prt, gen, n):
+    arr = scenegen.random_cloud(n, 5) if gen == "cloud" else scenegen.surface_scene(n, 6)
+    sc = prt.Scene.from_arrays(arr)
+    bvh = prt.build_bvh(sc, check=True)
+    hdr, nf, ni, prims, order = _parse_bvh(bvh.buffer, n)
+    assert hdr[0] == n
+    assert sorted(order.tolist()) == list(range(n))
+    assert np.array_equal(bvh.leaf_order().cpu().numpy(), order)
+    # every leaf reachable exactly once; children boxes nested in parents
+    seen_leaf = np.zeros(n, dtype=int)
+    seen_node = np.zeros(max(n - 1, 1), dtype=int)
+    stack = [(0, None)]
+    depth_max = 0
+    while stack:
+        node, box = stack.pop()
+        seen_node[node] += 1
+        rec = nf[node]
+        boxes = [rec[0:6], np.concatenate([rec[6:12]])]
+        lbox = np.array([rec[0], rec[1], rec[2], rec[3], rec[4], rec[5]])
+        rbox = np.array([rec[6], rec[7], rec[8], rec[9], rec[10], rec[11]])
+        refs = ni[node][12:14]
+        for ref, cb in zip(refs, (lbox, rbox)):
+            assert (cb[:3] <= cb[3:]).all()
+            if box is not None:
+                assert (cb[:3] >= box[:3]).all() and (cb[3:] <= box[3:]).all()
+            if ref < 0:
+                seen_leaf[~ref] += 1
+                # the leaf box holds the Gaussian's 3-sigma ellipsoid
+                j = order[~ref]
+                q = arr["quats"][j] / np.linalg.norm(arr["quats"][j])
+                w, x, y, z = q
+                R = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                              [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                              [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+                s = np.exp(arr["log_scales"][j])
+                h = 3 * np.sqrt((R ** 2) @ (s ** 2))
+                assert (cb[:3] <= arr["means"][j] - h + 1e-6).all() and (cb[3:] >= arr["means"][j] + h - 1e-6).all()
+            else:
+                stack.append((ref, cb))
+        del boxes
+    if n > 1:
+        assert (seen_node == 1).all()
+    assert (seen_leaf == 1).all()
+    # leaf records: centre, opacity and normal of the Gaussian in that leaf
+    assert np.allclose(prims[:, 0:3], arr["means"][order], atol=1e-6)
+    assert np.allclose(prims[:, 3], arr["opacity"][order], atol=1e-7)
+    assert np.allclose(prims[:, [7, 11, 15]], arr["normals"][order], atol=1e-6)
+    # Morton order: leaf centres sorted by their 30-bit codes
+    lo = arr["means"].astype(np.float32).min(0)
+    hi = arr["means"].astype(np.float32).max(0)
+    u = np.clip((arr["means"][order].astype(np.float32) - lo) / np.maximum(hi - lo, 1e-30), 0, 1)
+    q = np.minimum(np.floor(u * 1024), 1023).astype(np.int64)
+
+    def spread(v):
+        out = np.zeros_like(v)
+        for b in range(10):
+            out |= ((v >> b) & 1) << (3 * b)
+        return out
+    codes = (spread(q[:, 0]) << 2) | (spread(q[:, 1]) << 1) | spread(q[:, 2])
+    assert (np.diff(codes) >= 0).mean() > 0.999   # float rounding of the normalisation may differ at cell edges
+
+
+# ---------------------------------------------------------------------------
+# transfer parity
+# ---------------------------------------------------------------------------
+
+def test_transfer_cloud1k_full(prt, oracle_mod):
+    """The small workload in full: N = 1,000 random cloud, S = 64, 9 coeffs."""
+    w = scenegen.workload("cloud1k")
+    scene = as_f32(w["scene"])
+    params = prt.TransferParams(num_dirs=64, sh_bands=3)
+    _, _, (t, vis) = _run(prt, scene, params, want_vis=True)
+    ref = oracle_mod.direct_transfer(scene, 64, 3, want_vis=True, want_allow=True)
+    err = assert_transfer_parity(t.cpu().numpy()[:, 0, :], ref["t"], ref["allow"])
+    v = vis.cpu().numpy()
+    assert np.array_equal(v == -1, ref["vis"] == -1)        # the same rays are traced
+    traced = ref["vis"] != -1
+    dv = np.abs(v - ref["vis"])[traced]
+    assert (dv > 1e-5).mean() < 2e-3
+    print(f"cloud1k max |dt| = {err:.2e}, rays with |dV| > 1e-5: {(dv > 1e-5).sum()} of {dv.size}")
+
+
+@pytest.mark.parametrize("bands,S", [(1, 16), (2, 32), (4, 64)])
+def test_transfer_bands(prt, oracle_mod, bands, S):
+    scene = as_f32(scenegen.random_cloud(400, 77))
+    params = prt.TransferParams(num_dirs=S, sh_bands=bands, seed=5)
+    _, _, t = _run(prt, scene, params)
+    ref = oracle_mod.direct_transfer(scene, S, bands, seed=5, want_allow=True)
+    assert_transfer_parity(t.cpu().numpy()[:, 0, :], ref["t"], ref["allow"])
+
+
+def test_transfer_surface_sampled(prt, oracle_mod):
+    """Surface scene, 20k splats, S = 64, 16 coeffs; 300 sampled sources."""
+    scene = as_f32(scenegen.surface_scene(20000, 11))
+    params = prt.TransferParams(num_dirs=64, sh_bands=4)
+    _, _, t = _run(prt, scene, params)
+    src = np.random.default_rng(0).choice(20000, 300, replace=False)
+    ref = oracle_mod.direct_transfer(scene, 64, 4, sources=src, want_allow=True)
+    assert_transfer_parity(t.cpu().numpy()[src, 0, :], ref["t"], ref["allow"])
+
+
+def test_transfer_source_ranges(prt):
+    """Chunked runs over leaf ranges reproduce the single run bit for bit."""
+    import torch
+    scene = as_f32(scenegen.random_cloud(3000, 12))
+    sc = prt.Scene.from_arrays(scene)
+    bvh = prt.build_bvh(sc)
+    params = prt.TransferParams(num_dirs=64, sh_bands=3)
+    full = prt.precompute_transfer(sc, bvh, params)
+    part = torch.zeros_like(full)
+    for first in range(0, 3000, 700):
+        prt.precompute_transfer(sc, bvh, params, first=first, count=min(700, 3000 - first), out=part)
+    assert torch.equal(full, part)
+
+
+def test_transfer_degenerate(prt, oracle_mod):
+    """A single splat sees an empty scene; coincident centres; tiny scales."""
+    one = as_f32(scenegen.subset(scenegen.random_cloud(5, 1), [0]))
+    _, _, t = _run(prt, one, prt.TransferParams(num_dirs=256, sh_bands=4))
+    ref = oracle_mod.direct_transfer(one, 256, 4)
+    assert np.abs(t.cpu().numpy()[:, 0] - ref["t"]).max() < 1e-5
+    dup = as_f32(scenegen.random_cloud(64, 2))
+    dup["means"][:] = dup["means"][0]                # all centres equal: Morton codes all tie
+    _, _, t = _run(prt, dup, prt.TransferParams(num_dirs=64, sh_bands=3))
+    ref = oracle_mod.direct_transfer(dup, 64, 3, want_allow=True)
+    assert_transfer_parity(t.cpu().numpy()[:, 0], ref["t"], ref["allow"])
