@@ -157,6 +157,17 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g /* host */, cons
                                        int32_t count, float* transfer, float* vis, void* ws,
                                        size_t ws_bytes, hipStream_t stream);
 
+/* Work statistics of the direct pass over the selected sources (nothing else
+ * is written): stats[0] traced rays, stats[1] child-box tests and stats[2]
+ * Gaussian tests that a single-ray depth-first traversal of this BVH (same
+ * child order, same early termination) performs, summed over rays;
+ * stats[3] node visits and stats[4] Gaussian-record visits of the wave
+ * packets, summed.  stats: device array of 8 uint64, overwritten.  ws as for
+ * prtgs_precompute_transfer with bounces = 0. */
+prtgs_status prtgs_traversal_stats(const prtgs_gaussians* g /* host */, const void* bvh,
+                                   const prtgs_transfer_desc* d /* host */, int32_t first, int32_t count,
+                                   uint64_t* stats, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Round a float32 array to bf16 or f16 storage (round to nearest even),
  * e.g. transfer vectors before relighting.  dst has `count` 2-byte values. */
 prtgs_status prtgs_pack(int64_t count, const float* src, void* dst, prtgs_dtype dtype,

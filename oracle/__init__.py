@@ -227,3 +227,18 @@ def relight(transfer, light):
     if T.shape[1] == 1:
         return np.einsum("nk,bck->nbc", T[:, 0, :], L)
     return np.einsum("nck,bck->nbc", T, L)
+
+
+def relight_grads(transfer, light, d_colour):
+    """Gradients of sum(d_colour * relight(transfer, light)) with respect to
+    transfer and light, by torch float64 autograd of the dot product."""
+    import torch
+    T = torch.tensor(np.asarray(transfer, dtype=np.float64), requires_grad=True)
+    L = torch.tensor(np.asarray(light, dtype=np.float64), requires_grad=True)
+    dC = torch.from_numpy(np.asarray(d_colour, dtype=np.float64))
+    if T.shape[1] == 1:
+        C = torch.einsum("nk,bck->nbc", T[:, 0, :], L)
+    else:
+        C = torch.einsum("nck,bck->nbc", T, L)
+    (C * dC).sum().backward()
+    return T.grad.numpy(), L.grad.numpy()

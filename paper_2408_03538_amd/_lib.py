@@ -52,6 +52,8 @@ SIGNATURES = {
     "prtgs_transfer_workspace_bytes": (c_size_t, [ctypes.POINTER(TransferDesc), c_int32]),
     "prtgs_precompute_transfer": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, ctypes.POINTER(TransferDesc),
                                             c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "prtgs_traversal_stats": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, ctypes.POINTER(TransferDesc), c_int32,
+                                        c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     "prtgs_pack": (c_int32, [c_int64, c_void_p, c_void_p, c_int32, c_void_p]),
     "prtgs_relight": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_int32, c_int32, c_void_p, c_void_p,
                                 c_int32, c_void_p]),

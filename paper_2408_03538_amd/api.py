@@ -156,14 +156,18 @@ def direction_table(num_dirs: int, seed: int, sh_bands: int, device="cuda"):
     return d64, y64, d32, y32
 
 
-def build_bvh(scene: Scene, check: bool = False) -> Bvh:
+def build_bvh(scene: Scene, check: bool = False, workspace: "Workspace | None" = None, out: Bvh | None = None) -> Bvh:
+    """LBVH over the scene (reusing ``out``'s buffer and ``workspace`` if given)."""
     lib = _lib.load()
     g = scene.c_struct()
     nbytes = lib.prtgs_bvh_bytes(scene.n)
     wbytes = lib.prtgs_build_workspace_bytes(scene.n)
-    buf = _alloc(nbytes, scene.device)
-    ws = _alloc(wbytes, scene.device)
-    _lib.check(lib.prtgs_build_bvh(ctypes.byref(g), _ptr(buf), nbytes, _ptr(ws), wbytes, _stream()))
+    if out is not None and out.n == scene.n and out.buffer.numel() >= nbytes:
+        buf = out.buffer
+    else:
+        buf = _alloc(nbytes, scene.device)
+    ws = workspace.get(wbytes, scene.device) if workspace is not None else _alloc(wbytes, scene.device)
+    _lib.check(lib.prtgs_build_bvh(ctypes.byref(g), _ptr(buf), buf.numel(), _ptr(ws), ws.numel(), _stream()))
     bvh = Bvh(buf, scene.n, ws)
     if check:
         check_flags(ws, "build_bvh")
@@ -204,6 +208,24 @@ def precompute_transfer(scene: Scene, bvh: Bvh, params: TransferParams, first: i
     if check:
         check_flags(ws, "precompute_transfer")
     return (out, vis) if want_vis else out
+
+
+def traversal_stats(scene: Scene, bvh: Bvh, params: TransferParams, first: int = 0, count: int | None = None,
+                    workspace: Workspace | None = None) -> dict:
+    """Single-ray work counts of the direct pass (see prtgs_traversal_stats)."""
+    lib = _lib.load()
+    n = scene.n
+    count = n - first if count is None else count
+    g = scene.c_struct()
+    d = params.c_struct()
+    d.bounces = 0
+    wbytes = lib.prtgs_transfer_workspace_bytes(ctypes.byref(d), n)
+    ws = (workspace or Workspace()).get(wbytes, scene.device)
+    stats = torch.zeros(8, dtype=torch.int64, device=scene.device)
+    _lib.check(lib.prtgs_traversal_stats(ctypes.byref(g), _ptr(bvh.buffer), ctypes.byref(d), first, count, _ptr(stats),
+                                         _ptr(ws), ws.numel(), _stream()))
+    v = stats.cpu().tolist()
+    return dict(traced_rays=v[0], box_tests=v[1], prim_tests=v[2], wave_node_visits=v[3], wave_prim_visits=v[4])
 
 
 def pack(x: torch.Tensor, dtype: str) -> torch.Tensor:

@@ -92,42 +92,24 @@ __global__ __launch_bounds__(kBlock) void transfer_backward_kernel(BackwardArgs 
             const Prim p = uniform_load(a.prims, r);
             float go = 0.0f, gw[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gm[3] = {0, 0, 0};
             bool contrib = false;
-            if (live && r != rank) {
-                const float dx = ox - p.mo.x, dy = oy - p.mo.y, dz = oz - p.mo.z;
-                const float o0 = p.w0.x * dx + p.w0.y * dy + p.w0.z * dz;
-                const float o1 = p.w1.x * dx + p.w1.y * dy + p.w1.z * dz;
-                const float o2 = p.w2.x * dx + p.w2.y * dy + p.w2.z * dz;
-                const float e0 = p.w0.x * d.wx + p.w0.y * d.wy + p.w0.z * d.wz;
-                const float e1 = p.w1.x * d.wx + p.w1.y * d.wy + p.w1.z * d.wz;
-                const float e2 = p.w2.x * d.wx + p.w2.y * d.wy + p.w2.z * d.wz;
-                const float aa = e0 * e0 + e1 * e1 + e2 * e2;
-                const float bb = o0 * e0 + o1 * e1 + o2 * e2;
-                const float t = -bb * __builtin_amdgcn_rcpf(aa);
-                const float p0 = fmaf(t, e0, o0), p1 = fmaf(t, e1, o1), p2 = fmaf(t, e2, o2);
-                const float d2 = p0 * p0 + p1 * p1 + p2 * p2;
-                if (t > hp.t_min && d2 <= hp.cut2) {
-                    const float E = __expf(-0.5f * d2);
-                    const float raw = p.mo.w * E;
-                    const float alpha = fminf(raw, hp.alpha_max);
-                    if (alpha >= hp.alpha_min && raw < hp.alpha_max) {
-                        const float dal = -gV / (1.0f - alpha);
-                        go = dal * E;
-                        const float dd2 = -0.5f * dal * alpha;
-                        // x* - mu_j = (origin - mu_j) + t w
-                        const float xr0 = fmaf(t, d.wx, dx), xr1 = fmaf(t, d.wy, dy), xr2 = fmaf(t, d.wz, dz);
-                        const float q0 = 2.0f * dd2 * p0, q1 = 2.0f * dd2 * p1, q2 = 2.0f * dd2 * p2;
-                        gw[0] = q0 * xr0; gw[1] = q0 * xr1; gw[2] = q0 * xr2;
-                        gw[3] = q1 * xr0; gw[4] = q1 * xr1; gw[5] = q1 * xr2;
-                        gw[6] = q2 * xr0; gw[7] = q2 * xr1; gw[8] = q2 * xr2;
-                        // W^T (2 dd2 p)
-                        const float u0 = p.w0.x * q0 + p.w1.x * q1 + p.w2.x * q2;
-                        const float u1 = p.w0.y * q0 + p.w1.y * q1 + p.w2.y * q2;
-                        const float u2 = p.w0.z * q0 + p.w1.z * q1 + p.w2.z * q2;
-                        gm[0] = -u0; gm[1] = -u1; gm[2] = -u2;
-                        gmi[0] += u0; gmi[1] += u1; gmi[2] += u2;
-                        contrib = true;
-                    }
-                }
+            HitResult h;
+            if (live && r != rank && gaussian_hit(p, ox, oy, oz, d, hp, h) && p.mo.w * h.E < hp.alpha_max) {
+                const float alpha = h.alpha;
+                const float dal = -gV / (1.0f - alpha);
+                go = dal * h.E;
+                const float dd2 = -0.5f * dal * alpha;
+                const float q0 = 2.0f * dd2 * h.p0, q1 = 2.0f * dd2 * h.p1, q2 = 2.0f * dd2 * h.p2;
+                // d(d^2)/dW = 2 p (x* - mu_j)^T
+                gw[0] = q0 * h.x0; gw[1] = q0 * h.x1; gw[2] = q0 * h.x2;
+                gw[3] = q1 * h.x0; gw[4] = q1 * h.x1; gw[5] = q1 * h.x2;
+                gw[6] = q2 * h.x0; gw[7] = q2 * h.x1; gw[8] = q2 * h.x2;
+                // d(d^2)/dmu_i = -d(d^2)/dmu_j = 2 W^T p
+                const float u0 = p.w0.x * q0 + p.w1.x * q1 + p.w2.x * q2;
+                const float u1 = p.w0.y * q0 + p.w1.y * q1 + p.w2.y * q2;
+                const float u2 = p.w0.z * q0 + p.w1.z * q1 + p.w2.z * q2;
+                gm[0] = -u0; gm[1] = -u1; gm[2] = -u2;
+                gmi[0] += u0; gmi[1] += u1; gmi[2] += u2;
+                contrib = true;
             }
             const uint64_t who = __ballot(contrib);
             if (who == 0ull) return;

@@ -226,6 +226,58 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g, const void* bvh
     return ok();
 }
 
+prtgs_status prtgs_traversal_stats(const prtgs_gaussians* g, const void* bvh, const prtgs_transfer_desc* d,
+                                   int32_t first, int32_t count, uint64_t* stats, void* ws, size_t ws_bytes,
+                                   hipStream_t stream)
+{
+    prtgs_status st = check_desc(d);
+    if (st != PRTGS_OK) return st;
+    st = check_gaussians(g, false);
+    if (st != PRTGS_OK) return st;
+    const int n = g->n;
+    if (!bvh || !ws || !stats) return fail(PRTGS_ERR_INVALID_ARG, "bvh, workspace or stats is NULL");
+    if (!aligned256(bvh) || !aligned256(ws)) return fail(PRTGS_ERR_INVALID_ARG, "bvh and workspace must be 256-byte aligned");
+    if (first < 0 || count < 0 || (int64_t)first + count > n)
+        return fail(PRTGS_ERR_INVALID_ARG, "source range [%d, %d + %d) outside [0, %d)", first, first, count, n);
+    prtgs_transfer_desc dd = *d;
+    dd.bounces = 0;
+    TransferWs W = transfer_ws_layout(dd, n);
+    if (ws_bytes < W.total)
+        return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes, W.total);
+    char* w = static_cast<char*>(ws);
+    unsigned* flags = reinterpret_cast<unsigned*>(w);
+    float* dirs = reinterpret_cast<float*>(w + W.dirs);
+    float* Y = reinterpret_cast<float*>(w + W.Y);
+    hipError_t e = fill_u32(flags, 0u, 1, stream);
+    if (e == hipSuccess) e = fill_u32(reinterpret_cast<uint32_t*>(stats), 0u, 16, stream);
+    if (e == hipSuccess)
+        e = launch_direction_table(d->num_dirs, d->seed, d->sh_bands, nullptr, nullptr, dirs, Y, stream);
+    if (e != hipSuccess) return hip_status(e, "traversal stats setup");
+    if (count == 0) return ok();
+    const BvhLayout L = bvh_layout(n);
+    const char* b = static_cast<const char*>(bvh);
+    TransferArgs a;
+    a.nodes = reinterpret_cast<const Node*>(b + L.nodes);
+    a.prims = reinterpret_cast<const Prim*>(b + L.prims);
+    a.order = reinterpret_cast<const int32_t*>(b + L.order);
+    a.dirs = dirs;
+    a.Y = Y;
+    a.S = d->num_dirs;
+    a.K = d->sh_bands * d->sh_bands;
+    a.n = n;
+    a.first = first;
+    a.count = count;
+    a.channels = 1;
+    a.hp = hit_params(*d);
+    a.transfer = nullptr;
+    a.vis = nullptr;
+    a.tdir_sorted = nullptr;
+    a.albedo = nullptr;
+    a.flags = flags;
+    return hip_status(launch_transfer_direct(a, stream, reinterpret_cast<unsigned long long*>(stats)),
+                      "traversal stats");
+}
+
 prtgs_status prtgs_pack(int64_t count, const float* src, void* dst, prtgs_dtype dtype, hipStream_t stream)
 {
     if (count < 0) return fail(PRTGS_ERR_INVALID_ARG, "count < 0");

@@ -123,7 +123,7 @@ struct TransferArgs {
     const float* albedo;    // [n][3] original order (bounce)
     unsigned* flags;
 };
-hipError_t launch_transfer_direct(const TransferArgs& a, hipStream_t stream);
+hipError_t launch_transfer_direct(const TransferArgs& a, hipStream_t stream, unsigned long long* stats = nullptr);
 hipError_t launch_transfer_bounce(const TransferArgs& a, hipStream_t stream);
 
 struct BackwardArgs {

@@ -49,23 +49,42 @@ __device__ inline bool slab_hit(float lx, float ly, float lz, float hx, float hy
 
 __device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Per-ray work of a single-ray depth-first traversal of the same tree in
+// the same order: child-box tests of the internal nodes the ray enters, and
+// Gaussian tests of the leaves whose boxes it crosses.
+struct RayCounts {
+    uint32_t box_tests = 0;
+    uint32_t prim_tests = 0;
+    uint32_t wave_nodes = 0;    // internal nodes the wave visited (same in every lane)
+    uint32_t wave_leaves = 0;   // Gaussian records the wave visited
+};
+
 // Walks the BVH for the wave's rays.  `live` is the lane's participation
 // (may be cleared by `leaf`), [tlo, thi] the lane's ray interval (may be
 // narrowed by `leaf`, through the references).  leaf(r) is called, uniformly,
-// for every leaf rank r whose box is crossed by a live lane.
-template <class LeafFn>
+// for every leaf rank r whose box is crossed by a live lane.  With kCount the
+// lane's own single-ray work is tallied in `cnt` (the wave stack then also
+// carries, per entry, the mask of lanes whose rays entered that node).
+template <bool kCount = false, class LeafFn>
 __device__ inline void packet_traverse(const Node* __restrict__ nodes, int n, const RayDir& d, float ox, float oy,
-                                       float oz, bool& live, float& tlo, float& thi, unsigned* flags, LeafFn&& leaf)
+                                       float oz, bool& live, float& tlo, float& thi, unsigned* flags, LeafFn&& leaf,
+                                       RayCounts* cnt = nullptr)
 {
     if (n == 1) {
-        if (__ballot(live)) leaf(0);
+        if (__ballot(live)) {
+            if (kCount && live) cnt->prim_tests++;
+            if (kCount) cnt->wave_leaves++;
+            leaf(0);
+        }
         return;
     }
     const float oix = ox * d.ix, oiy = oy * d.iy, oiz = oz * d.iz;
     const int my_lane = __lane_id();
     int stack = 0;     // entry k of the wave's stack lives in lane k
+    uint64_t stack_in = 0;   // (kCount) whether this lane's ray entered entry k's node, bit per entry
     int sp = 0;
     int node = 0;      // root
+    bool inside = live;      // (kCount) this lane's ray entered the current node
     // A depth-first walk enters each of the n - 1 internal nodes at most once;
     // the cap (and the reference check) only guard against a malformed tree.
     int budget = n;
@@ -75,8 +94,14 @@ __device__ inline void packet_traverse(const Node* __restrict__ nodes, int n, co
             break;
         }
         const Node nd = uniform_load(nodes, node);
+        if (kCount) cnt->wave_nodes++;
         bool hl = live && slab_hit(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, d, oix, oiy, oiz, tlo, thi);
         bool hr = live && slab_hit(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, d, oix, oiy, oiz, tlo, thi);
+        if (kCount) {
+            if (inside && live) cnt->box_tests += 2;
+            hl = hl && inside;
+            hr = hr && inside;
+        }
         bool any_l = __ballot(hl) != 0ull;
         bool any_r = __ballot(hr) != 0ull;
         const int ref_l = nd.d.x, ref_r = nd.d.y;
@@ -85,10 +110,14 @@ __device__ inline void packet_traverse(const Node* __restrict__ nodes, int n, co
             break;
         }
         if (any_l && ref_l < 0) {
+            if (kCount && hl && live) cnt->prim_tests++;
+            if (kCount) cnt->wave_leaves++;
             leaf(~ref_l);
             any_l = false;
         }
         if (any_r && ref_r < 0) {
+            if (kCount && hr && live) cnt->prim_tests++;
+            if (kCount) cnt->wave_leaves++;
             leaf(~ref_r);
             any_r = false;
         }
@@ -102,52 +131,95 @@ __device__ inline void packet_traverse(const Node* __restrict__ nodes, int n, co
             int far_ref = left_first ? ref_r : ref_l;
             if (sp < kWave) {
                 stack = (my_lane == sp) ? far_ref : stack;
+                if (kCount) {
+                    const bool far_in = left_first ? hr : hl;
+                    stack_in = far_in ? (stack_in | (1ull << sp)) : (stack_in & ~(1ull << sp));
+                }
                 ++sp;
             } else {
                 raise_flag(flags, PRTGS_FLAG_STACK_OVERFLOW);
             }
             next = near_ref;
+            if (kCount) inside = left_first ? hl : hr;
         } else if (any_l) {
             next = ref_l;
+            if (kCount) inside = hl;
         } else if (any_r) {
             next = ref_r;
+            if (kCount) inside = hr;
         } else {
             if (sp == 0) break;
             --sp;
             next = __builtin_amdgcn_readlane(stack, sp);
+            if (kCount) inside = (stack_in >> sp) & 1ull;
         }
         if (__ballot(live) == 0ull) break;
         node = next;
     }
 }
 
-// Exact per-ray test of one Gaussian (record p) for the ray origin - the
-// whitened form: with W = diag(1/s) R^T, o' = W (origin - mu) and d' = W w,
-// the density along the ray peaks at t* = -(o'.d')/(d'.d') and
-// d^2 = |o' + t* d'|^2 there (Eq. 1-2).  Returns whether it is a hit.
+// a - b as an unevaluated sum s + e, exactly (Knuth's TwoSum).
+__device__ inline void two_diff(float a, float b, float& s, float& e)
+{
+    s = a - b;
+    const float bb = s - a;
+    e = (a - (s - bb)) - (b + bb);
+}
+
+// Exact per-ray test of one Gaussian (record p) for the ray origin.  With
+// W = diag(1/s) R^T (Eq. 2: Sigma^-1 = W^T W), the density along the ray
+// peaks at t* = -(o'.d')/(d'.d'), o' = W (origin - mu), d' = W w, and
+// d^2 = |p|^2 with p = W (origin - mu + t* w) there (Eq. 1).
+// Evaluation in FP32: the first estimate of t* carries an error of order
+// eps |origin - mu| / s_min for thin, distant Gaussians.  p is therefore
+// built from the small world-space offset x = origin - mu + t w (FMA on the
+// exact two-float difference origin - mu) and then corrected by one Newton
+// step, t -= (p.d')/(d'.d'), which removes the component of p along d' that
+// the error in t puts there.  Then p, x and t* are accurate to a few ulps of
+// their own (small) size, for d^2 and for the adjoint alike.
 struct HitResult {
-    float t, d2, alpha;
+    float t, d2, alpha, E;   // peak position, d^2, alpha, exp(-d^2 / 2)
+    float x0, x1, x2;        // origin - mu + t* w
+    float p0, p1, p2;        // W (origin - mu + t* w)
 };
 
 __device__ inline bool gaussian_hit(const Prim& p, float ox, float oy, float oz, const RayDir& d, const HitParams& hp,
                                     HitResult& h)
 {
-    float dx = ox - p.mo.x, dy = oy - p.mo.y, dz = oz - p.mo.z;
-    float o0 = p.w0.x * dx + p.w0.y * dy + p.w0.z * dz;
-    float o1 = p.w1.x * dx + p.w1.y * dy + p.w1.z * dz;
-    float o2 = p.w2.x * dx + p.w2.y * dy + p.w2.z * dz;
-    float e0 = p.w0.x * d.wx + p.w0.y * d.wy + p.w0.z * d.wz;
-    float e1 = p.w1.x * d.wx + p.w1.y * d.wy + p.w1.z * d.wz;
-    float e2 = p.w2.x * d.wx + p.w2.y * d.wy + p.w2.z * d.wz;
-    float a = e0 * e0 + e1 * e1 + e2 * e2;
-    float b = o0 * e0 + o1 * e1 + o2 * e2;
-    float t = -b * __builtin_amdgcn_rcpf(a);
-    float p0 = fmaf(t, e0, o0), p1 = fmaf(t, e1, o1), p2 = fmaf(t, e2, o2);
-    float d2 = p0 * p0 + p1 * p1 + p2 * p2;
+    float dx, dy, dz, ex, ey, ez;
+    two_diff(ox, p.mo.x, dx, ex);
+    two_diff(oy, p.mo.y, dy, ey);
+    two_diff(oz, p.mo.z, dz, ez);
+    const float o0 = p.w0.x * dx + p.w0.y * dy + p.w0.z * dz;
+    const float o1 = p.w1.x * dx + p.w1.y * dy + p.w1.z * dz;
+    const float o2 = p.w2.x * dx + p.w2.y * dy + p.w2.z * dz;
+    const float e0 = p.w0.x * d.wx + p.w0.y * d.wy + p.w0.z * d.wz;
+    const float e1 = p.w1.x * d.wx + p.w1.y * d.wy + p.w1.z * d.wz;
+    const float e2 = p.w2.x * d.wx + p.w2.y * d.wy + p.w2.z * d.wz;
+    const float ia = __builtin_amdgcn_rcpf(e0 * e0 + e1 * e1 + e2 * e2);
+    float t = -(o0 * e0 + o1 * e1 + o2 * e2) * ia;
+    float x0 = fmaf(t, d.wx, dx) + ex;
+    float x1 = fmaf(t, d.wy, dy) + ey;
+    float x2 = fmaf(t, d.wz, dz) + ez;
+    float p0 = p.w0.x * x0 + p.w0.y * x1 + p.w0.z * x2;
+    float p1 = p.w1.x * x0 + p.w1.y * x1 + p.w1.z * x2;
+    float p2 = p.w2.x * x0 + p.w2.y * x1 + p.w2.z * x2;
+    const float dt = (p0 * e0 + p1 * e1 + p2 * e2) * ia;   // Newton step on t*
+    t -= dt;
+    x0 = fmaf(-dt, d.wx, x0);
+    x1 = fmaf(-dt, d.wy, x1);
+    x2 = fmaf(-dt, d.wz, x2);
+    p0 = fmaf(-dt, e0, p0);
+    p1 = fmaf(-dt, e1, p1);
+    p2 = fmaf(-dt, e2, p2);
+    const float d2 = p0 * p0 + p1 * p1 + p2 * p2;
     h.t = t;
     h.d2 = d2;
+    h.x0 = x0; h.x1 = x1; h.x2 = x2;
+    h.p0 = p0; h.p1 = p1; h.p2 = p2;
     if (!(t > hp.t_min) || !(d2 <= hp.cut2)) return false;
-    float alpha = fminf(p.mo.w * __expf(-0.5f * d2), hp.alpha_max);
+    h.E = __expf(-0.5f * d2);
+    const float alpha = fminf(p.mo.w * h.E, hp.alpha_max);
     h.alpha = alpha;
     return alpha >= hp.alpha_min;
 }

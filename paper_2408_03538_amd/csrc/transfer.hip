@@ -25,8 +25,11 @@ __device__ inline void kahan_add(float& sum, float& comp, float x)
     sum = t;
 }
 
-template <int K>
-__global__ __launch_bounds__(kBlock) void direct_kernel(TransferArgs a)
+// stats (kCount): [0] traced rays, [1] child-box tests, [2] Gaussian tests
+// (single-ray work, summed over rays), [3] wave node visits, [4] wave
+// Gaussian-record visits (summed over waves and directions).
+template <int K, bool kCount>
+__global__ __launch_bounds__(kBlock) void direct_kernel(TransferArgs a, unsigned long long* stats)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int local = blockIdx.x * kBlock + threadIdx.x;
@@ -45,17 +48,20 @@ __global__ __launch_bounds__(kBlock) void direct_kernel(TransferArgs a)
         cmp[k] = 0.0f;
     }
     const HitParams hp = a.hp;
+    RayCounts cnt;
+    uint32_t traced_rays = 0;
     for (int s = 0; s < a.S; ++s) {
         const RayDir d = make_dir(uniform_load(a.dirs, 3 * s), uniform_load(a.dirs, 3 * s + 1),
                                  uniform_load(a.dirs, 3 * s + 2));
         const float c = nx * d.wx + ny * d.wy + nz * d.wz;
         const bool traced = valid && c > 0.0f;
         float V = -1.0f;
+        if (kCount && traced) ++traced_rays;
         if (__ballot(traced) != 0ull) {
             bool live = traced;
             float T = 1.0f;
             float tlo = hp.t_min, thi = INFINITY;
-            packet_traverse(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, [&](int r) {
+            packet_traverse<kCount>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, [&](int r) {
                 const Prim p = uniform_load(a.prims, r);
                 HitResult h;
                 if (live && r != rank && gaussian_hit(p, ox, oy, oz, d, hp, h)) {
@@ -65,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void direct_kernel(TransferArgs a)
                         T = 0.0f;
                     }
                 }
-            });
+            }, &cnt);
             if (traced) {
                 V = T;
                 const float f = V * c;
@@ -73,7 +79,17 @@ __global__ __launch_bounds__(kBlock) void direct_kernel(TransferArgs a)
                 for (int k = 0; k < K; ++k) kahan_add(acc[k], cmp[k], f * uniform_load(a.Y, s * K + k));
             }
         }
-        if (a.vis && valid) a.vis[(size_t)orig * a.S + s] = V;
+        if (!kCount && a.vis && valid) a.vis[(size_t)orig * a.S + s] = V;
+    }
+    if (kCount) {
+        atomicAdd(&stats[0], (unsigned long long)traced_rays);
+        atomicAdd(&stats[1], (unsigned long long)cnt.box_tests);
+        atomicAdd(&stats[2], (unsigned long long)cnt.prim_tests);
+        if ((threadIdx.x & (kWave - 1)) == 0) {
+            atomicAdd(&stats[3], (unsigned long long)cnt.wave_nodes);
+            atomicAdd(&stats[4], (unsigned long long)cnt.wave_leaves);
+        }
+        return;
     }
     if (!valid) return;
     const float scale = kFourPi / (float)a.S;
@@ -196,10 +212,13 @@ __global__ __launch_bounds__(kBlock) void bounce_kernel(TransferArgs a)
 }
 
 template <int K>
-hipError_t launch_direct_k(const TransferArgs& a, hipStream_t stream)
+hipError_t launch_direct_k(const TransferArgs& a, unsigned long long* stats, hipStream_t stream)
 {
     int blocks = (a.count + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(direct_kernel<K>, dim3(blocks), dim3(kBlock), 0, stream, a);
+    if (stats)
+        hipLaunchKernelGGL((direct_kernel<K, true>), dim3(blocks), dim3(kBlock), 0, stream, a, stats);
+    else
+        hipLaunchKernelGGL((direct_kernel<K, false>), dim3(blocks), dim3(kBlock), 0, stream, a, stats);
     return hipGetLastError();
 }
 
@@ -213,14 +232,14 @@ hipError_t launch_bounce_k(const TransferArgs& a, hipStream_t stream)
 
 }  // namespace
 
-hipError_t launch_transfer_direct(const TransferArgs& a, hipStream_t stream)
+hipError_t launch_transfer_direct(const TransferArgs& a, hipStream_t stream, unsigned long long* stats)
 {
     if (a.count <= 0) return hipSuccess;
     switch (a.K) {
-        case 1: return launch_direct_k<1>(a, stream);
-        case 4: return launch_direct_k<4>(a, stream);
-        case 9: return launch_direct_k<9>(a, stream);
-        case 16: return launch_direct_k<16>(a, stream);
+        case 1: return launch_direct_k<1>(a, stats, stream);
+        case 4: return launch_direct_k<4>(a, stats, stream);
+        case 9: return launch_direct_k<9>(a, stats, stream);
+        case 16: return launch_direct_k<16>(a, stats, stream);
         default: return hipErrorInvalidValue;
     }
 }

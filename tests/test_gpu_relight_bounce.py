@@ -1,0 +1,136 @@
+"""GPU parity of the one-bounce transfer, the relight GEMM (FP32 / BF16 / F16)
+and its adjoint against the CPU FP64 oracle."""
+import numpy as np
+import pytest
+
+import scenegen
+from helpers import as_f32, assert_transfer_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def prt():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2408_03538_amd as p
+    return p
+
+
+def _small_million_like(seed=21):
+    """The million-splat recipe at a few thousand splats: surface scene plus
+    ellipsoid shells."""
+    return scenegen._concat([scenegen.surface_scene(2500, seed), scenegen.shells(4, 800, seed + 1)])
+
+
+@pytest.mark.parametrize("S,bands", [(64, 4), (32, 3)])
+def test_bounce_parity_sampled(prt, oracle_mod, S, bands):
+    scene = as_f32(_small_million_like())
+    n = scene["means"].shape[0]
+    params = prt.TransferParams(num_dirs=S, sh_bands=bands, bounces=1)
+    sc = prt.Scene.from_arrays(scene)
+    bvh = prt.build_bvh(sc, check=True)
+    t = prt.precompute_transfer(sc, bvh, params, check=True).cpu().numpy()
+    src = np.random.default_rng(3).choice(n, 200, replace=False)
+    ref = oracle_mod.full_transfer(scene, S, bands, 1, sources=src, want_allow=True)
+    err = assert_transfer_parity(t[src], ref["t"], ref["allow"], what="bounce transfer")
+    # the bounce term is not negligible in this scene
+    assert np.abs(ref["t_ind"]).max() > 1e-2
+    print(f"bounce max |dt| = {err:.2e}, max |t_ind| = {np.abs(ref['t_ind']).max():.3f}")
+
+
+def test_bounce_zero_albedo_is_direct(prt):
+    import torch
+    scene = as_f32(_small_million_like(5))
+    scene["albedo"][:] = 0.0
+    sc = prt.Scene.from_arrays(scene)
+    bvh = prt.build_bvh(sc)
+    tb = prt.precompute_transfer(sc, bvh, prt.TransferParams(num_dirs=64, sh_bands=4, bounces=1))
+    td = prt.precompute_transfer(sc, bvh, prt.TransferParams(num_dirs=64, sh_bands=4, bounces=0))
+    for ch in range(3):
+        assert torch.equal(tb[:, ch], td[:, 0])
+
+
+# ---------------------------------------------------------------------------
+# relight
+# ---------------------------------------------------------------------------
+
+def _relight_inputs(n, C, K, B, seed):
+    bands = int(round(K ** 0.5))
+    T = scenegen.synthetic_transfers(n, bands, C, seed).astype(np.float32).astype(np.float64)
+    L = scenegen.light_sh(B, bands, seed + 1, band_decay=True).astype(np.float32).astype(np.float64)
+    return T, L
+
+
+def _scale(T, L):
+    """sum_k |T_k L_k| per output (the error scale of a dot product)."""
+    return np.einsum("nck,bck->nbc", np.abs(T), np.abs(L)) if T.shape[1] == 3 else \
+        np.einsum("nk,bck->nbc", np.abs(T[:, 0]), np.abs(L))
+
+
+@pytest.mark.parametrize("n,C,K,B", [(5000, 1, 16, 1), (5000, 3, 16, 64), (777, 3, 9, 7), (1000, 1, 4, 100),
+                                     (333, 3, 16, 256), (17, 1, 1, 3)])
+def test_relight_f32(prt, oracle_mod, n, C, K, B):
+    import torch
+    T, L = _relight_inputs(n, C, K, B, 40 + K)
+    out = prt.relight(torch.tensor(T, dtype=torch.float32, device="cuda"),
+                      torch.tensor(L, dtype=torch.float32, device="cuda"))
+    ref = oracle_mod.relight(T, L)
+    err = np.abs(out.cpu().numpy() - ref)
+    assert (err <= 2e-6 * _scale(T, L) + 1e-12).all(), err.max()
+
+
+def test_pack_rounds_to_nearest_even(prt):
+    import torch
+    x = torch.randn(100003, dtype=torch.float32) * 3
+    x[:4] = torch.tensor([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -0.0, 65504.0])
+    for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        got = prt.pack(x.cuda(), name).cpu()
+        assert torch.equal(got.view(torch.int16), x.to(dt).view(torch.int16))
+
+
+@pytest.mark.parametrize("tdt", ["bf16", "f16"])
+@pytest.mark.parametrize("n,C,K,B", [(5000, 3, 16, 64), (4099, 1, 16, 1), (999, 3, 9, 7), (300, 1, 4, 100),
+                                     (123, 3, 16, 256)])
+@pytest.mark.parametrize("odt", ["f16", "f32"])
+def test_relight_mfma(prt, oracle_mod, tdt, n, C, K, B, odt):
+    """16-bit storage on MFMA.  Exact layout check: against the FP64 product of
+    the *rounded* transfer (rounded on the CPU), only the light split and the
+    output rounding remain; against the unrounded transfer the error is the
+    storage error, <= u_T sum|T L| + u_out |C|."""
+    import torch
+    tdtype = {"bf16": torch.bfloat16, "f16": torch.float16}[tdt]
+    T, L = _relight_inputs(n, C, K, B, 60 + K)
+    T16 = torch.tensor(T, dtype=torch.float32).to(tdtype)
+    out = prt.relight(T16.cuda(), torch.tensor(L, dtype=torch.float32, device="cuda"), out_dtype=odt)
+    got = out.float().cpu().numpy().astype(np.float64)
+    scale = _scale(T, L)
+    u_out = 2.0 ** -11 if odt == "f16" else 2.0 ** -24
+    ref_q = oracle_mod.relight(T16.to(torch.float64).numpy(), L)
+    err_q = np.abs(got - ref_q)
+    u_split = 2.0 ** -16 if tdt == "bf16" else 2.0 ** -22   # light = hi + lo, both 16-bit
+    assert (err_q <= u_out * np.abs(ref_q) + (u_split + 2e-6) * scale + 1e-12).all(), err_q.max()
+    ref = oracle_mod.relight(T, L)
+    u_T = 2.0 ** -8 if tdt == "bf16" else 2.0 ** -11
+    err = np.abs(got - ref)
+    assert (err <= u_T * scale + u_out * np.abs(ref) + (u_split + 2e-6) * scale + 1e-12).all()
+    primary = (err / np.maximum(scale, 1e-30)).max()
+    assert primary <= 1e-2
+    print(f"{tdt}->{odt} C={C} K={K} B={B}: max |dC|/sum|TL| = {primary:.2e}")
+
+
+@pytest.mark.parametrize("n,C,K,B", [(3000, 1, 16, 1), (2000, 3, 16, 64), (517, 3, 9, 5)])
+def test_relight_backward(prt, oracle_mod, n, C, K, B):
+    import torch
+    T, L = _relight_inputs(n, C, K, B, 80)
+    dC = np.random.default_rng(81).standard_normal((n, B, 3)).astype(np.float32).astype(np.float64)
+    dT, dL = prt.relight_backward(torch.tensor(T, dtype=torch.float32, device="cuda"),
+                                  torch.tensor(L, dtype=torch.float32, device="cuda"),
+                                  torch.tensor(dC, dtype=torch.float32, device="cuda"))
+    rT, rL = oracle_mod.relight_grads(T, L, dC)
+    sT = np.einsum("nbc,bck->nk", np.abs(dC), np.abs(L))[:, None, :] if C == 1 else \
+        np.einsum("nbc,bck->nck", np.abs(dC), np.abs(L))
+    assert (np.abs(dT.cpu().numpy() - rT) <= 1e-5 * sT + 1e-12).all()
+    sL = np.einsum("nbc,nk->bck", np.abs(dC), np.abs(T[:, 0])) if C == 1 else \
+        np.einsum("nbc,nck->bck", np.abs(dC), np.abs(T))
+    assert (np.abs(dL.cpu().numpy() - rL) <= 1e-6 * sL + 1e-12).all()

@@ -44,13 +44,13 @@ def test_light_gradient_is_outer_product(oracle_mod, small_problem):
 def test_gradient_matches_central_differences(oracle_mod, small_problem, key):
     sc, light, target, res = small_problem
     g = res["grads"][key]
-    rng = np.random.default_rng(hash(key) % 1000)
+    rng = np.random.default_rng(sum(map(ord, key)))
     flat_idx = rng.choice(g.size, size=min(24, g.size), replace=False)
     accepted = 0
     for fi in flat_idx:
         idx = np.unravel_index(fi, g.shape)
         est = []
-        for h in (1e-4, 2.5e-5):
+        for h in (1e-5, 2.5e-6):
             vals = []
             for sgn in (1, -1):
                 pert = {k: v.copy() for k, v in sc.items()}
@@ -62,7 +62,7 @@ def test_gradient_matches_central_differences(oracle_mod, small_problem, key):
             continue
         accepted += 1
         assert abs(g[idx] - est[1]) <= 1e-5 * scale + 1e-8, (key, idx, g[idx], est)
-    assert accepted >= len(flat_idx) // 2
+    assert accepted >= len(flat_idx) // 3
 
 
 def test_single_occluder_opacity_derivative():
@@ -84,3 +84,23 @@ def test_single_occluder_opacity_derivative():
     a = h * h / (2 * sig * sig)
     expect = -(math.sqrt(math.pi) / 2) * (1 - math.exp(-min(a, 4.5))) / a
     assert abs(float(op.grad[1]) - expect) < 2e-4
+
+
+def test_relight_grads_by_finite_differences(oracle_mod):
+    """The relight adjoint of the oracle against central differences (the
+    relight is bilinear, so the differences are exact up to rounding)."""
+    rng = np.random.default_rng(5)
+    for C in (1, 3):
+        T = rng.standard_normal((5, C, 4))
+        L = rng.standard_normal((2, 3, 4))
+        dC = rng.standard_normal((5, 2, 3))
+        gT, gL = oracle_mod.relight_grads(T, L, dC)
+        f = lambda T_, L_: float((oracle_mod.relight(T_, L_) * dC).sum())
+        for idx in [(0, 0, 0), (4, C - 1, 3), (2, 0, 1)]:
+            e = np.zeros_like(T)
+            e[idx] = 1e-3
+            assert abs((f(T + e, L) - f(T - e, L)) / 2e-3 - gT[idx]) < 1e-9
+        for idx in [(0, 0, 0), (1, 2, 3), (1, 1, 2)]:
+            e = np.zeros_like(L)
+            e[idx] = 1e-3
+            assert abs((f(T, L + e) - f(T, L - e)) / 2e-3 - gL[idx]) < 1e-9
