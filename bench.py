@@ -1,17 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark of the PRTGS transfer precompute on one MI355X.
 
-A step is one pass of the whole hot path over the million-splat workload
-(surface scene 200k + 20 ellipsoid shells x 40k = 1,000,000 Gaussians,
-S = 512 directions, 16 SH coefficients, RGB transfer with one interreflection
-bounce): BVH build, direct transfer, bounce, and relighting under one light.
-`value` is nominal rays (N * S) per second of the whole step, inputs already
-resident on the GPU.  Secondary measurements (relight throughput in FP32 /
-BF16 / F16 on 3M splats x 64 lights, forward vs forward + backward on 200k
-splats) and the CPU oracle baseline are added as extra fields of the same
-JSON line.
+A step is one pass of the hot path over the 100k-splat surface workload (a
+unit sphere on a 4x4 plane, 100,000 Gaussians, S = 256 directions, 16 SH
+coefficients, direct visibility transfer): BVH build, transfer precompute
+and relighting under one light.  `value` is nominal rays (N * S) per second
+of the whole step, inputs already resident on the GPU.  The same JSON line
+carries the secondary measurements: the million-splat workload with one
+interreflection bounce, relighting 3M splats x 64 lights with FP32 vs BF16 /
+F16 storage, forward vs forward + backward on 200k splats, and the CPU oracle
+baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+    python bench.py --copy-mib M      # plain device copy (counter calibration)
 """
 from __future__ import annotations
 
@@ -38,6 +39,24 @@ FLOPS_PER_BOX_TEST = 15
 FLOPS_PER_PRIM_TEST = 70
 
 
+# HBM traffic of the direct kernel on this workload, from two rocprofv3
+# counter runs (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy): see
+# profiles/direct_kernel_surface100k_hbm_counters.md.  Valid only for the
+# kernel sources it was measured on (hash below); null otherwise.
+MEASURED_TRAFFIC = {"sources_sha256_16": "b081a0a91f25d5bf", "bytes_per_launch": 7.830e9}
+KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
+                  "paper_2408_03538_amd/csrc/common.hpp"]
+
+
+def kernel_sources_hash():
+    import hashlib
+    m = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            m.update(f.read())
+    return m.hexdigest()[:16]
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -45,11 +64,12 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true", help="skip the relight and backward measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sources", type=int, default=12, help="sampled sources of the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle baseline budget")
+    ap.add_argument("--copy-mib", type=int, default=0, help="only run a plain device copy of this size")
     return ap.parse_args()
 
 
@@ -74,14 +94,26 @@ class Timer:
         return [a.elapsed_time(b) for a, b in self.marks.get(name, [])]
 
 
-def million_step_setup(prt, torch, scenegen):
+def workload_setup(prt, torch, scenegen, name):
     import numpy as np
-    w = scenegen.workload("million")
+    w = scenegen.workload(name)
     arr = {k: np.asarray(v, dtype=np.float32) for k, v in w["scene"].items()}
     sc = prt.Scene.from_arrays(arr)
     params = prt.TransferParams(num_dirs=w["num_dirs"], sh_bands=w["bands"], bounces=w["bounces"])
     light = torch.tensor(w["light"], dtype=torch.float32, device="cuda")
     return arr, sc, params, light
+
+
+def copy_only(mib):
+    """A plain device-to-device copy of `mib` MiB (read + write), for scaling
+    the HBM byte counters."""
+    import torch
+    x = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}))
 
 
 def main():
@@ -90,6 +122,9 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_mib:
+        copy_only(args.copy_mib)
+        return
     import numpy as np
     import torch
 
@@ -98,93 +133,45 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    log("generating the million-splat workload")
-    arr, sc, params, light = million_step_setup(prt, torch, scenegen)
+    log("generating the 100k surface workload")
+    arr, sc, params, light = workload_setup(prt, torch, scenegen, "surface100k")
     n, S = sc.n, params.num_dirs
+    res = time_steps(prt, torch, np, sc, params, light, args.steps, args.warmup)
+    ms_step = res["ms_step"]
+    log(f"step {ms_step:.2f} ms: build {res['build']:.3f} ms, transfer {res['transfer']:.2f} ms, "
+        f"relight {res['relight']:.4f} ms")
 
-    # buffers allocated once, outside the timed region
-    ws_build = prt.Workspace()
-    ws_tr = prt.Workspace()
-    transfer = torch.zeros((n, params.channels, params.K), dtype=torch.float32, device="cuda")
-    colour = torch.empty((n, 1, 3), dtype=torch.float32, device="cuda")
-    bvh_holder = {}
-    timer = Timer(torch)
-
-    def step(record=True):
-        if record:
-            timer.start("build")
-        bvh = prt.build_bvh(sc, workspace=ws_build, out=bvh_holder.get("bvh"))
-        bvh_holder["bvh"] = bvh
-        if record:
-            timer.stop("build")
-            timer.start("transfer")
-        prt.precompute_transfer(sc, bvh, params, out=transfer, workspace=ws_tr)
-        if record:
-            timer.stop("transfer")
-            timer.start("relight")
-        prt.relight(transfer, light, out=colour)
-        if record:
-            timer.stop("relight")
-
-    log("warmup")
-    for _ in range(args.warmup):
-        step(record=False)
-    torch.cuda.synchronize()
-    prt.check_flags(ws_tr.buf, "transfer")
-    log(f"timing {args.steps} steps")
-    timer.marks.clear()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = wall * 1e3 / args.steps
-    t_build = float(np.mean(timer.ms("build")))
-    t_transfer = float(np.mean(timer.ms("transfer")))
-    t_relight = float(np.mean(timer.ms("relight")))
-    log(f"step {ms_step:.1f} ms: build {t_build:.2f} ms, transfer {t_transfer:.1f} ms, relight {t_relight:.3f} ms")
-
-    # split of the transfer into its two traversal passes, and the per-ray work
-    direct_params = prt.TransferParams(num_dirs=S, sh_bands=params.sh_bands, bounces=0)
-    direct_out = torch.zeros((n, 1, params.K), dtype=torch.float32, device="cuda")
-    ws_d = prt.Workspace()
-    for _ in range(1):
-        prt.precompute_transfer(sc, bvh_holder["bvh"], direct_params, out=direct_out, workspace=ws_d)
-    tdir = []
-    for _ in range(max(2, args.steps)):
-        timer.start("direct")
-        prt.precompute_transfer(sc, bvh_holder["bvh"], direct_params, out=direct_out, workspace=ws_d)
-        timer.stop("direct")
-    torch.cuda.synchronize()
-    t_direct = float(np.mean(timer.ms("direct")))
-    t_bounce = t_transfer - t_direct
-    stats = prt.traversal_stats(sc, bvh_holder["bvh"], direct_params)
+    stats = prt.traversal_stats(sc, res["bvh"], params)
     traced = stats["traced_rays"]
     n_box = stats["box_tests"] / traced
     n_prim = stats["prim_tests"] / traced
-    log(f"direct {t_direct:.1f} ms, bounce {t_bounce:.1f} ms; per traced ray: {n_box:.1f} box tests, "
-        f"{n_prim:.1f} Gaussian tests; packet visits {stats['wave_node_visits']} nodes")
     b_ray = BYTES_PER_BOX_TEST * n_box + BYTES_PER_PRIM_TEST * n_prim
     f_ray = FLOPS_PER_BOX_TEST * n_box + FLOPS_PER_PRIM_TEST * n_prim
-    direct_rays_per_s = traced / (t_direct * 1e-3)
-    achieved_flops = direct_rays_per_s * f_ray / 1e12
+    t_kernel = res["transfer"]
+    rays_per_s = traced / (t_kernel * 1e-3)
+    achieved = rays_per_s * b_ray / 1e9
+    log(f"per traced ray: {n_box:.1f} box tests, {n_prim:.1f} Gaussian tests = {b_ray:.0f} algorithmic bytes; "
+        f"{achieved:.0f} GB/s algorithmic")
     roofline = {
         "kernel": "direct_kernel (visibility traversal + SH projection)",
-        "bound": "alu",
-        "achieved": round(achieved_flops, 3),
-        "peak": PEAK_FP32_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(achieved_flops / PEAK_FP32_TFLOPS, 4),
-        "traffic": None,
-        "per_ray": {"box_tests": round(n_box, 2), "prim_tests": round(n_prim, 2),
-                    "algorithmic_bytes": round(b_ray, 1), "algorithmic_flops": round(f_ray, 1)},
-        "hbm_implied": {"rays_per_s_at_8TBps": round(PEAK_HBM_GBS * 1e9 / b_ray, 1),
-                        "measured_rays_per_s": round(direct_rays_per_s, 1),
-                        "frac": round(direct_rays_per_s / (PEAK_HBM_GBS * 1e9 / b_ray), 4)},
-        "ms_per_launch": round(t_direct, 3),
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / PEAK_HBM_GBS, 4),
+        "traffic": (MEASURED_TRAFFIC["bytes_per_launch"]
+                    if kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"] else None),
+        "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "units_per_launch": traced,
+        "unit_of_work": "traced ray",
+        "algorithmic_bytes_per_unit": round(b_ray, 1),
+        "per_ray": {"box_tests": round(n_box, 2), "prim_tests": round(n_prim, 2)},
+        "ms_per_launch": round(t_kernel, 4),
+        "alu_view": {"algorithmic_flops_per_ray": round(f_ray, 1),
+                     "achieved_TFLOPs": round(rays_per_s * f_ray / 1e12, 3), "peak_TFLOPs": PEAK_FP32_TFLOPS,
+                     "packet_node_visits_per_64_rays": round(stats["wave_node_visits"] / (traced / 64), 1),
+                     "packet_gaussian_visits_per_64_rays": round(stats["wave_prim_visits"] / (traced / 64), 1)},
     }
-
     value = n * S / (ms_step * 1e-3) / 1e9
     result = {
         "metric": "transfer precompute Grays/s + relit splats/s; BF16 vs FP32, fwd+bwd vs fwd",
@@ -193,33 +180,105 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
+        "ms_per_step": round(ms_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "million: surface scene 200k + 20 shells x 40k, S=512, 16 SH coeffs, RGB + 1 bounce",
+        "config": {"workload": "surface100k: unit sphere on a 4x4 plane, N=100,000, S=256, 16 SH coeffs, direct",
                    "n_splats": n, "num_dirs": S, "sh_coeffs": params.K, "channels": params.channels,
                    "bounces": params.bounces},
-        "breakdown_ms": {"build_bvh": round(t_build, 3), "transfer": round(t_transfer, 3),
-                         "direct_pass": round(t_direct, 3), "bounce_pass": round(t_bounce, 3),
-                         "relight": round(t_relight, 4)},
-        "traced_grays_per_s_direct": round(direct_rays_per_s / 1e9, 4),
+        "breakdown_ms": {"build_bvh": round(res["build"], 4), "transfer": round(res["transfer"], 4),
+                         "relight": round(res["relight"], 5)},
+        "traced_grays_per_s": round(rays_per_s / 1e9, 4),
+        "relit_splats_per_s": round(n / (res["relight"] * 1e-3), 1),
         "traced_rays": traced,
         "roofline": roofline,
     }
-
-    del transfer, direct_out, colour
-    bvh_holder.clear()
-    ws_build.buf = ws_tr.buf = ws_d.buf = None
+    res.clear()
     torch.cuda.empty_cache()
     if not args.no_extras:
-        result["relight"] = bench_relight(prt, torch, scenegen, np, args.steps)
-        result["backward"] = bench_backward(prt, torch, scenegen, np, args.steps)
+        result["million_bounce"] = bench_million(prt, torch, scenegen, np)
+        result["relight_3m"] = bench_relight(prt, torch, scenegen, np, args.steps)
+        result["backward_200k"] = bench_backward(prt, torch, scenegen, np, args.steps)
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(arr, params, args.cpu_sources)
+        result["cpu_baseline"] = cpu_baseline(arr, params, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+def time_steps(prt, torch, np, sc, params, light, steps, warmup):
+    """Whole-step timing (wall clock around synchronised steps) plus HIP
+    events around each library call, on the stream the library launches on."""
+    ws_build, ws_tr = prt.Workspace(), prt.Workspace()
+    transfer = torch.zeros((sc.n, params.channels, params.K), dtype=torch.float32, device="cuda")
+    colour = torch.empty((sc.n, light.shape[0], 3), dtype=torch.float32, device="cuda")
+    holder = {}
+    timer = Timer(torch)
+
+    def step(record):
+        if record:
+            timer.start("build")
+        holder["bvh"] = prt.build_bvh(sc, workspace=ws_build, out=holder.get("bvh"))
+        if record:
+            timer.stop("build")
+            timer.start("transfer")
+        prt.precompute_transfer(sc, holder["bvh"], params, out=transfer, workspace=ws_tr)
+        if record:
+            timer.stop("transfer")
+            timer.start("relight")
+        prt.relight(transfer, light, out=colour)
+        if record:
+            timer.stop("relight")
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    prt.check_flags(ws_tr.buf, "transfer")
+    timer.marks.clear()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"ms_step": wall * 1e3 / steps, "build": float(np.mean(timer.ms("build"))),
+            "transfer": float(np.mean(timer.ms("transfer"))), "relight": float(np.mean(timer.ms("relight"))),
+            "bvh": holder["bvh"], "transfer_out": transfer}
+
+
+def bench_million(prt, torch, scenegen, np):
+    """1,000,000 splats, S=512, 16 coeffs, RGB with one bounce: one timed
+    step (build + direct + bounce + relight) after one warm-up step."""
+    log("million-splat workload with one bounce")
+    arr, sc, params, light = workload_setup(prt, torch, scenegen, "million")
+    res = time_steps(prt, torch, np, sc, params, light, 1, 1)
+    direct = prt.TransferParams(num_dirs=params.num_dirs, sh_bands=params.sh_bands, bounces=0)
+    out = torch.zeros((sc.n, 1, params.K), dtype=torch.float32, device="cuda")
+    ws = prt.Workspace()
+    prt.precompute_transfer(sc, res["bvh"], direct, out=out, workspace=ws)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    prt.precompute_transfer(sc, res["bvh"], direct, out=out, workspace=ws)
+    b.record()
+    torch.cuda.synchronize()
+    t_direct = a.elapsed_time(b)
+    stats = prt.traversal_stats(sc, res["bvh"], direct)
+    traced = stats["traced_rays"]
+    n_box, n_prim = stats["box_tests"] / traced, stats["prim_tests"] / traced
+    b_ray = BYTES_PER_BOX_TEST * n_box + BYTES_PER_PRIM_TEST * n_prim
+    out_d = {"workload": "million: surface scene 200k + 20 shells x 40k, S=512, 16 coeffs, RGB + 1 bounce",
+             "ms_per_step": round(res["ms_step"], 2),
+             "nominal_grays_per_s": round(sc.n * params.num_dirs / (res["ms_step"] * 1e-3) / 1e9, 4),
+             "breakdown_ms": {"build_bvh": round(res["build"], 3), "direct_pass": round(t_direct, 2),
+                              "bounce_pass": round(res["transfer"] - t_direct, 2), "relight": round(res["relight"], 4)},
+             "direct_traced_grays_per_s": round(traced / (t_direct * 1e-3) / 1e9, 4),
+             "per_ray": {"box_tests": round(n_box, 2), "prim_tests": round(n_prim, 2),
+                         "algorithmic_bytes": round(b_ray, 1)},
+             "direct_hbm_implied_frac": round(traced / (t_direct * 1e-3) * b_ray / 1e9 / PEAK_HBM_GBS, 4)}
+    log(f"million: step {res['ms_step']:.0f} ms, direct {t_direct:.0f} ms")
+    del res, out
+    torch.cuda.empty_cache()
+    return out_d
 
 
 def bench_relight(prt, torch, scenegen, np, steps):
@@ -311,35 +370,35 @@ def bench_backward(prt, torch, scenegen, np, steps):
     return res
 
 
-def cpu_baseline(arr, params, count):
-    """The oracle (brute force, FP64, all host cores) on sampled sources of
-    the same workload: direct pass plus the bounce pass (the bounce's
-    per-ray cost does not depend on the values of the hit splats' direct
-    transfers, which are set to zero here)."""
+def cpu_baseline(arr, params, seconds):
+    """The oracle (brute force over all Gaussians per ray, FP64, all host
+    cores) on randomly sampled sources of the same workload, in batches until
+    the time budget is spent."""
     import numpy as np
 
     import oracle
     oracle.build()
     scene = {k: v.astype(np.float64) for k, v in arr.items()}
     n = scene["means"].shape[0]
-    src = np.random.default_rng(7).choice(n, count, replace=False)
     threads = oracle.default_threads()
-    log(f"cpu baseline: oracle on {count} sources, {threads} threads")
+    rng = np.random.default_rng(7)
+    log(f"cpu baseline: oracle, {threads} threads, ~{seconds:.0f} s")
+    done = 0
     t0 = time.perf_counter()
-    oracle.direct_transfer(scene, params.num_dirs, params.sh_bands, sources=src, margins=None, threads=threads)
-    t1 = time.perf_counter()
-    zeros = np.zeros((n, params.K))
-    oracle.bounce_transfer(scene, params.num_dirs, params.sh_bands, zeros, np.arange(n), sources=src, threads=threads)
-    t2 = time.perf_counter()
-    rays = count * params.num_dirs
-    value = rays / (t2 - t0) / 1e9
+    batch = max(threads, 16)
+    while time.perf_counter() - t0 < seconds:
+        src = rng.choice(n, batch, replace=False)
+        oracle.direct_transfer(scene, params.num_dirs, params.sh_bands, sources=src, margins=None, threads=threads)
+        done += batch
+    elapsed = time.perf_counter() - t0
+    value = done * params.num_dirs / elapsed / 1e9
     try:
-        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+        model = [ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")][0]
     except (OSError, IndexError):
         model = "unknown"
     return {"value": value, "unit": "Grays/s (nominal N*S rays per second)", "cores": threads, "kind": "oracle",
-            "sample": f"{count} random sources of the million-splat workload, direct + bounce passes "
-                      f"({t1 - t0:.1f} s + {t2 - t1:.1f} s), brute force over all 1M Gaussians per ray, FP64",
+            "sample": f"{done} random sources of the 100k surface workload ({done * params.num_dirs} nominal rays, "
+                      f"{elapsed:.1f} s), each traced ray tested against all {n} Gaussians, FP64",
             "cpu_model": model}
 
 

@@ -187,9 +187,10 @@ prtgs_status prtgs_relight(int32_t n, int32_t K, int32_t C, const void* transfer
                            int32_t B, const float* light, void* colour, prtgs_dtype out_dtype,
                            hipStream_t stream);
 
-/* Adjoint of prtgs_relight for F32 transfer and colour:
- *   d_transfer[i][c'][k] (+)= sum_b sum_{c -> c'} d_colour[i][b][c] light[b][c][k]  (overwritten)
- *   d_light[b][c][k]      = sum_i d_colour[i][b][c] transfer[i][c'][k]            (overwritten)
+/* Adjoint of prtgs_relight for F32 transfer and colour (both outputs are
+ * overwritten, not accumulated):
+ *   d_transfer[i][c'][k] = sum_b sum_{c mapped to c'} d_colour[i][b][c] light[b][c][k]
+ *   d_light[b][c][k]     = sum_i d_colour[i][b][c] transfer[i][c'][k]  (compensated sums)
  * Either output may be NULL.  ws: prtgs_relight_backward_workspace_bytes. */
 size_t prtgs_relight_backward_workspace_bytes(int32_t n, int32_t K, int32_t C, int32_t B);
 prtgs_status prtgs_relight_backward(int32_t n, int32_t K, int32_t C, const float* transfer, int32_t B,

@@ -30,17 +30,59 @@ __device__ inline float wave_sum(float v)
     return v;
 }
 
+__device__ inline float segment_sum(float v, int D)
+{
+    for (int off = D / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+struct BatchDir {
+    float mean[3];
+    int oct;
+    bool uniform_oct;
+};
+
+// Mean direction of the traced lanes and whether they share an octant.
+__device__ inline BatchDir batch_dir(const RayDir& d, bool traced)
+{
+    BatchDir b;
+    b.mean[0] = traced ? d.wx : 0.0f;
+    b.mean[1] = traced ? d.wy : 0.0f;
+    b.mean[2] = traced ? d.wz : 0.0f;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) b.mean[q] = wave_sum(b.mean[q]);
+    const int first = __builtin_ctzll(__ballot(traced));
+    const int oct = octant(d);
+    b.oct = __builtin_amdgcn_readlane(oct, first);
+    b.uniform_oct = __ballot(traced && oct != b.oct) == 0ull;
+    return b;
+}
+
+template <class LeafFn>
+__device__ inline void traverse_batch(const TransferArgs& a, const RayDir& d, const BatchDir& bd, float ox, float oy,
+                                      float oz, bool& live, float& tlo, float& thi, LeafFn& leaf)
+{
+    if (bd.uniform_oct)
+        packet_traverse<false, true>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf, nullptr, bd.mean,
+                                     bd.oct);
+    else
+        packet_traverse<false, false>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf, nullptr, bd.mean, 0);
+}
+
 template <int K>
 __global__ __launch_bounds__(kBlock) void transfer_backward_kernel(BackwardArgs ba)
 {
     const TransferArgs& a = ba.fwd;
     const int lane = threadIdx.x & (kWave - 1);
-    const int local = blockIdx.x * kBlock + threadIdx.x;
+    const int G = a.G;
+    const int D = kWave / G;
+    const int gwave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const int local = gwave * G + lane / D;
     const bool valid = local < a.count;
     const int rank = valid ? local : 0;
-    const Prim src = a.prims[rank];
-    const float ox = src.mo.x, oy = src.mo.y, oz = src.mo.z;
-    const float nx = src.w0.w, ny = src.w1.w, nz = src.w2.w;
+    const float4 mo = a.prims[rank].mo;
+    const float ox = mo.x, oy = mo.y, oz = mo.z;
+    const float4 nrm = a.normals[rank];
     const int orig = a.order[rank];
     const HitParams hp = a.hp;
 
@@ -51,31 +93,36 @@ __global__ __launch_bounds__(kBlock) void transfer_backward_kernel(BackwardArgs 
     float gni[3] = {0.0f, 0.0f, 0.0f};   // dLoss/dn_i
     const float wq = kFourPi / (float)a.S;
 
-    for (int s = 0; s < a.S; ++s) {
-        const RayDir d = make_dir(uniform_load(a.dirs, 3 * s), uniform_load(a.dirs, 3 * s + 1),
-                                 uniform_load(a.dirs, 3 * s + 2));
-        const float c = nx * d.wx + ny * d.wy + nz * d.wz;
+    for (int b0 = 0; b0 < a.S; b0 += D) {
+        const int pos = b0 + (lane % D);
+        const bool inrange = pos < a.S;
+        const int s = inrange ? a.dir_order[pos] : 0;
+        const RayDir d = make_dir(a.dirs[3 * s], a.dirs[3 * s + 1], a.dirs[3 * s + 2]);
+        const float c = nrm.x * d.wx + nrm.y * d.wy + nrm.z * d.wz;
+        const bool traced = valid && inrange && c > 0.0f;
+        if (__ballot(traced) == 0ull) continue;
         float g = 0.0f;
 #pragma unroll
-        for (int k = 0; k < K; ++k) g = fmaf(dt[k], uniform_load(a.Y, s * K + k), g);
+        for (int k = 0; k < K; ++k) g = fmaf(dt[k], a.Y[(size_t)s * K + k], g);
         g *= wq;
-        const bool traced = valid && c > 0.0f;
-        if (__ballot(traced) == 0ull) continue;
+        const BatchDir bd = batch_dir(d, traced);
         // pass 1: transmittance
         bool live = traced;
         float T = 1.0f;
         float tlo = hp.t_min, thi = INFINITY;
-        packet_traverse(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, [&](int r) {
+        auto leaf1 = [&](int r, bool box_hit) {
             const Prim p = uniform_load(a.prims, r);
+            const PreHit q = gaussian_pre(p, ox, oy, oz, d, hp);
+            const bool cand = q.maybe & box_hit & live & (r != rank);
+            if (__ballot(cand) == 0ull) return;
             HitResult h;
-            if (live && r != rank && gaussian_hit(p, ox, oy, oz, d, hp, h)) {
-                T *= 1.0f - h.alpha;
-                if (T < hp.T_eps) {
-                    live = false;
-                    T = 0.0f;
-                }
-            }
-        });
+            const bool hit = gaussian_exact(p, q, ox, oy, oz, d, hp, h) & cand;
+            T = hit ? T * (1.0f - h.alpha) : T;
+            const bool opaque = T < hp.T_eps;
+            live = live & !opaque;
+            T = opaque ? 0.0f : T;
+        };
+        traverse_batch(a, d, bd, ox, oy, oz, live, tlo, thi, leaf1);
         const bool carries = traced && T > 0.0f;
         if (carries) {
             gni[0] += g * T * d.wx;
@@ -83,17 +130,21 @@ __global__ __launch_bounds__(kBlock) void transfer_backward_kernel(BackwardArgs 
             gni[2] += g * T * d.wz;
         }
         if (__ballot(carries && g != 0.0f) == 0ull) continue;
-        // pass 2: per-hit adjoint
+        // pass 2: per-hit adjoint (the same hits: these lanes ran pass 1 to the end)
         const float gV = g * c * T;   // dLoss/dV times V
         live = carries && g != 0.0f;
         tlo = hp.t_min;
         thi = INFINITY;
-        packet_traverse(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, [&](int r) {
+        auto leaf2 = [&](int r, bool box_hit) {
             const Prim p = uniform_load(a.prims, r);
-            float go = 0.0f, gw[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gm[3] = {0, 0, 0};
-            bool contrib = false;
+            const PreHit q = gaussian_pre(p, ox, oy, oz, d, hp);
+            const bool cand = q.maybe & box_hit & live & (r != rank);
+            if (__ballot(cand) == 0ull) return;
             HitResult h;
-            if (live && r != rank && gaussian_hit(p, ox, oy, oz, d, hp, h) && p.mo.w * h.E < hp.alpha_max) {
+            const bool hit = gaussian_exact(p, q, ox, oy, oz, d, hp, h) & cand;
+            const bool contrib = hit & (p.mo.w * h.E < hp.alpha_max);   // a clamped alpha has no gradient
+            float go = 0.0f, gw[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gm[3] = {0, 0, 0};
+            if (contrib) {
                 const float alpha = h.alpha;
                 const float dal = -gV / (1.0f - alpha);
                 go = dal * h.E;
@@ -109,31 +160,36 @@ __global__ __launch_bounds__(kBlock) void transfer_backward_kernel(BackwardArgs 
                 const float u2 = p.w0.z * q0 + p.w1.z * q1 + p.w2.z * q2;
                 gm[0] = -u0; gm[1] = -u1; gm[2] = -u2;
                 gmi[0] += u0; gmi[1] += u1; gmi[2] += u2;
-                contrib = true;
             }
             const uint64_t who = __ballot(contrib);
             if (who == 0ull) return;
             if (__popcll(who) == 1) {
                 if (contrib) {
                     atomicAdd(&ba.g_o[r], go);
-                    for (int q = 0; q < 9; ++q) atomicAdd(&ba.g_W[9 * (size_t)r + q], gw[q]);
-                    for (int q = 0; q < 3; ++q) atomicAdd(&ba.g_mu[3 * (size_t)r + q], gm[q]);
+                    for (int k = 0; k < 9; ++k) atomicAdd(&ba.g_W[9 * (size_t)r + k], gw[k]);
+                    for (int k = 0; k < 3; ++k) atomicAdd(&ba.g_mu[3 * (size_t)r + k], gm[k]);
                 }
                 return;
             }
             go = wave_sum(go);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) gw[q] = wave_sum(gw[q]);
+            for (int k = 0; k < 9; ++k) gw[k] = wave_sum(gw[k]);
 #pragma unroll
-            for (int q = 0; q < 3; ++q) gm[q] = wave_sum(gm[q]);
+            for (int k = 0; k < 3; ++k) gm[k] = wave_sum(gm[k]);
             if (lane == 0) {
                 atomicAdd(&ba.g_o[r], go);
-                for (int q = 0; q < 9; ++q) atomicAdd(&ba.g_W[9 * (size_t)r + q], gw[q]);
-                for (int q = 0; q < 3; ++q) atomicAdd(&ba.g_mu[3 * (size_t)r + q], gm[q]);
+                for (int k = 0; k < 9; ++k) atomicAdd(&ba.g_W[9 * (size_t)r + k], gw[k]);
+                for (int k = 0; k < 3; ++k) atomicAdd(&ba.g_mu[3 * (size_t)r + k], gm[k]);
             }
-        });
+        };
+        traverse_batch(a, d, bd, ox, oy, oz, live, tlo, thi, leaf2);
     }
-    if (!valid) return;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        gmi[q] = segment_sum(gmi[q], D);
+        gni[q] = segment_sum(gni[q], D);
+    }
+    if (!valid || (lane % D) != 0) return;
     for (int q = 0; q < 3; ++q) {
         atomicAdd(&ba.g_mu[3 * (size_t)rank + q], gmi[q]);
         ba.g_n[3 * (size_t)rank + q] = gni[q];
@@ -192,7 +248,8 @@ __global__ void backward_finalize_kernel(BackwardArgs ba)
 template <int K>
 hipError_t launch_bwd_k(const BackwardArgs& a, hipStream_t stream)
 {
-    int blocks = (a.fwd.count + kBlock - 1) / kBlock;
+    int waves = (a.fwd.count + a.fwd.G - 1) / a.fwd.G;
+    int blocks = (waves + kBlock / kWave - 1) / (kBlock / kWave);
     hipLaunchKernelGGL(transfer_backward_kernel<K>, dim3(blocks), dim3(kBlock), 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

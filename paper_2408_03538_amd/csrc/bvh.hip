@@ -236,7 +236,8 @@ __global__ void radix_scatter_kernel(const uint32_t* __restrict__ kin, const int
 // R diag(s^2) R^T (Eq. 2), padded for rounding.
 
 __global__ void leaf_kernel(const prtgs_gaussians g, const int32_t* __restrict__ order, Prim* __restrict__ prims,
-                            float* __restrict__ leafbox, int32_t* __restrict__ order_out, unsigned* flags)
+                            float4* __restrict__ normals, float* __restrict__ leafbox, int32_t* __restrict__ order_out,
+                            unsigned* flags)
 {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= g.n) return;
@@ -270,10 +271,11 @@ __global__ void leaf_kernel(const prtgs_gaussians g, const int32_t* __restrict__
     float is[3] = {expf(-l0), expf(-l1), expf(-l2)};
     Prim p;
     p.mo = make_float4(mx, my, mz, op);
-    p.w0 = make_float4(R[0][0] * is[0], R[1][0] * is[0], R[2][0] * is[0], nx);
-    p.w1 = make_float4(R[0][1] * is[1], R[1][1] * is[1], R[2][1] * is[1], ny);
-    p.w2 = make_float4(R[0][2] * is[2], R[1][2] * is[2], R[2][2] * is[2], nz);
+    p.w0 = make_float4(R[0][0] * is[0], R[1][0] * is[0], R[2][0] * is[0], fmaxf(is[0], fmaxf(is[1], is[2])));
+    p.w1 = make_float4(R[0][1] * is[1], R[1][1] * is[1], R[2][1] * is[1], 0.0f);
+    p.w2 = make_float4(R[0][2] * is[2], R[1][2] * is[2], R[2][2] * is[2], 0.0f);
     prims[r] = p;
+    normals[r] = make_float4(nx, ny, nz, 0.0f);
     float m[3] = {mx, my, mz};
     float mag = fmaxf(fabsf(mx), fmaxf(fabsf(my), fabsf(mz)));
     for (int a = 0; a < 3; ++a) {
@@ -382,6 +384,7 @@ hipError_t launch_build_bvh(const prtgs_gaussians& g, void* bvh, void* ws, unsig
     BvhHeader* hdr = reinterpret_cast<BvhHeader*>(b);
     Node* nodes = reinterpret_cast<Node*>(b + L.nodes);
     Prim* prims = reinterpret_cast<Prim*>(b + L.prims);
+    float4* normals = reinterpret_cast<float4*>(b + L.normals);
     int32_t* order_out = reinterpret_cast<int32_t*>(b + L.order);
     uint32_t* keys[2] = {reinterpret_cast<uint32_t*>(w + W.keys0), reinterpret_cast<uint32_t*>(w + W.keys1)};
     int32_t* vals[2] = {reinterpret_cast<int32_t*>(w + W.vals0), reinterpret_cast<int32_t*>(w + W.vals1)};
@@ -414,8 +417,8 @@ hipError_t launch_build_bvh(const prtgs_gaussians& g, void* bvh, void* ws, unsig
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
-    hipLaunchKernelGGL(leaf_kernel, dim3(blocks), dim3(256), 0, stream, g, vals[cur], prims, leafbox, order_out,
-                       flags);
+    hipLaunchKernelGGL(leaf_kernel, dim3(blocks), dim3(256), 0, stream, g, vals[cur], prims, normals, leafbox,
+                       order_out, flags);
     if (n > 1) {
         if ((e = fill_u32(counters, 0u, (size_t)(n - 1), stream)) != hipSuccess) return e;
         int iblocks = (n - 1 + 255) / 256;

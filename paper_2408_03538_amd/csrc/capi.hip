@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "common.hpp"
@@ -70,7 +71,7 @@ prtgs_status check_desc(const prtgs_transfer_desc* d)
 }
 
 struct TransferWs {
-    size_t dirs, Y, tdir, total;
+    size_t dirs, Y, dir_order, tdir, albedo, total;
 };
 
 TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
@@ -82,15 +83,33 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     off += align256(sizeof(float) * 3 * (size_t)d.num_dirs);
     w.Y = off;
     off += align256(sizeof(float) * (size_t)K * (size_t)d.num_dirs);
+    w.dir_order = off;
+    off += align256(sizeof(int32_t) * (size_t)d.num_dirs);
     w.tdir = off;
     if (d.bounces) off += align256(sizeof(float) * (size_t)K * (size_t)n);
+    w.albedo = off;
+    if (d.bounces) off += align256(sizeof(float) * 4 * (size_t)n);
     w.total = off;
     return w;
+}
+
+// Sources per wave of the group split: as many as keep >= 8192 waves in
+// flight (256 CUs x 32), at most 16; 1 selects the fan kernel.
+int group_size(int count)
+{
+    int G = 16;
+    while (G > 1 && count / G < 8192) G >>= 1;
+    if (const char* env = getenv("PRTGS_GROUP")) {
+        int g = atoi(env);
+        if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64) G = g;
+    }
+    return G;
 }
 
 HitParams hit_params(const prtgs_transfer_desc& d)
 {
     HitParams h;
+    h.cut = d.sigma_cut;
     h.cut2 = d.sigma_cut * d.sigma_cut;
     h.t_min = d.t_min;
     h.T_eps = d.T_eps;
@@ -194,6 +213,7 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g, const void* bvh
     hipError_t e = fill_u32(flags, 0u, 1, stream);
     if (e == hipSuccess)
         e = launch_direction_table(d->num_dirs, d->seed, d->sh_bands, nullptr, nullptr, dirs, Y, stream);
+    if (e == hipSuccess) e = launch_direction_order(d->num_dirs, reinterpret_cast<int32_t*>(w + W.dir_order), stream);
     if (e != hipSuccess) return hip_status(e, "direction table");
     if (count == 0) return ok();
 
@@ -202,9 +222,11 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g, const void* bvh
     TransferArgs a;
     a.nodes = reinterpret_cast<const Node*>(b + L.nodes);
     a.prims = reinterpret_cast<const Prim*>(b + L.prims);
+    a.normals = reinterpret_cast<const float4*>(b + L.normals);
     a.order = reinterpret_cast<const int32_t*>(b + L.order);
     a.dirs = dirs;
     a.Y = Y;
+    a.dir_order = reinterpret_cast<const int32_t*>(w + W.dir_order);
     a.S = d->num_dirs;
     a.K = d->sh_bands * d->sh_bands;
     a.n = n;
@@ -216,6 +238,8 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g, const void* bvh
     a.vis = vis;
     a.tdir_sorted = d->bounces ? reinterpret_cast<float*>(w + W.tdir) : nullptr;
     a.albedo = g->albedo;
+    a.albedo_sorted = d->bounces ? reinterpret_cast<float4*>(w + W.albedo) : nullptr;
+    a.G = group_size(count);
     a.flags = flags;
     e = launch_transfer_direct(a, stream);
     if (e != hipSuccess) return hip_status(e, "direct transfer");
@@ -252,6 +276,7 @@ prtgs_status prtgs_traversal_stats(const prtgs_gaussians* g, const void* bvh, co
     if (e == hipSuccess) e = fill_u32(reinterpret_cast<uint32_t*>(stats), 0u, 16, stream);
     if (e == hipSuccess)
         e = launch_direction_table(d->num_dirs, d->seed, d->sh_bands, nullptr, nullptr, dirs, Y, stream);
+    if (e == hipSuccess) e = launch_direction_order(d->num_dirs, reinterpret_cast<int32_t*>(w + W.dir_order), stream);
     if (e != hipSuccess) return hip_status(e, "traversal stats setup");
     if (count == 0) return ok();
     const BvhLayout L = bvh_layout(n);
@@ -259,9 +284,11 @@ prtgs_status prtgs_traversal_stats(const prtgs_gaussians* g, const void* bvh, co
     TransferArgs a;
     a.nodes = reinterpret_cast<const Node*>(b + L.nodes);
     a.prims = reinterpret_cast<const Prim*>(b + L.prims);
+    a.normals = reinterpret_cast<const float4*>(b + L.normals);
     a.order = reinterpret_cast<const int32_t*>(b + L.order);
     a.dirs = dirs;
     a.Y = Y;
+    a.dir_order = reinterpret_cast<const int32_t*>(w + W.dir_order);
     a.S = d->num_dirs;
     a.K = d->sh_bands * d->sh_bands;
     a.n = n;
@@ -273,6 +300,8 @@ prtgs_status prtgs_traversal_stats(const prtgs_gaussians* g, const void* bvh, co
     a.vis = nullptr;
     a.tdir_sorted = nullptr;
     a.albedo = nullptr;
+    a.albedo_sorted = nullptr;
+    a.G = group_size(count);
     a.flags = flags;
     return hip_status(launch_transfer_direct(a, stream, reinterpret_cast<unsigned long long*>(stats)),
                       "traversal stats");
@@ -360,6 +389,7 @@ prtgs_status prtgs_transfer_backward(const prtgs_gaussians* g, const void* bvh, 
     hipError_t e = fill_u32(flags, 0u, 1, stream);
     if (e == hipSuccess)
         e = launch_direction_table(d->num_dirs, d->seed, d->sh_bands, nullptr, nullptr, dirs, Y, stream);
+    if (e == hipSuccess) e = launch_direction_order(d->num_dirs, reinterpret_cast<int32_t*>(w + W.dir_order), stream);
     if (e == hipSuccess) e = fill_u32(reinterpret_cast<uint32_t*>(scratch), 0u, 16 * (size_t)n, stream);
     if (e != hipSuccess) return hip_status(e, "backward setup");
 
@@ -368,9 +398,11 @@ prtgs_status prtgs_transfer_backward(const prtgs_gaussians* g, const void* bvh, 
     BackwardArgs a;
     a.fwd.nodes = reinterpret_cast<const Node*>(b + L.nodes);
     a.fwd.prims = reinterpret_cast<const Prim*>(b + L.prims);
+    a.fwd.normals = reinterpret_cast<const float4*>(b + L.normals);
     a.fwd.order = reinterpret_cast<const int32_t*>(b + L.order);
     a.fwd.dirs = dirs;
     a.fwd.Y = Y;
+    a.fwd.dir_order = reinterpret_cast<const int32_t*>(w + W.dir_order);
     a.fwd.S = d->num_dirs;
     a.fwd.K = d->sh_bands * d->sh_bands;
     a.fwd.n = n;
@@ -382,6 +414,8 @@ prtgs_status prtgs_transfer_backward(const prtgs_gaussians* g, const void* bvh, 
     a.fwd.vis = nullptr;
     a.fwd.tdir_sorted = nullptr;
     a.fwd.albedo = nullptr;
+    a.fwd.albedo_sorted = nullptr;
+    a.fwd.G = group_size(n);
     a.fwd.flags = flags;
     a.d_transfer = d_transfer;
     a.g_W = scratch;

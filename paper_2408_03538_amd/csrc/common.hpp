@@ -26,12 +26,12 @@ struct __align__(16) Node {
 
 // Ray-test record of one Gaussian, in leaf order: centre and opacity, then
 // the rows of the whitening matrix W = diag(1/s) R^T (so that W^T W is the
-// inverse covariance of Eq. 2) with the normal's components in .w.
+// inverse covariance of Eq. 2); w0.w holds 1 / min(s) (rounding bounds).
 struct __align__(16) Prim {
     float4 mo;   // mu.x, mu.y, mu.z, opacity
-    float4 w0;   // W row 0, normal.x
-    float4 w1;   // W row 1, normal.y
-    float4 w2;   // W row 2, normal.z
+    float4 w0;   // W row 0, 1 / s_min
+    float4 w1;   // W row 1, 0
+    float4 w2;   // W row 2, 0
 };
 
 struct BvhHeader {
@@ -42,8 +42,10 @@ struct BvhHeader {
     float hi[4];
 };
 
+// BVH buffer: header | internal nodes | Gaussian records | normals (float4,
+// leaf order) | leaf-to-Gaussian permutation.
 struct BvhLayout {
-    size_t nodes, prims, order, total;
+    size_t nodes, prims, normals, order, total;
 };
 
 inline BvhLayout bvh_layout(int n)
@@ -54,6 +56,8 @@ inline BvhLayout bvh_layout(int n)
     off += align256(sizeof(Node) * (size_t)(n > 1 ? n - 1 : 1));
     L.prims = off;
     off += align256(sizeof(Prim) * (size_t)n);
+    L.normals = off;
+    off += align256(sizeof(float4) * (size_t)n);
     L.order = off;
     off += align256(sizeof(int32_t) * (size_t)n);
     L.total = off;
@@ -62,6 +66,7 @@ inline BvhLayout bvh_layout(int n)
 
 // Cutoffs of the hit test, as used on the device.
 struct HitParams {
+    float cut;        // sigma_cut
     float cut2;       // sigma_cut^2
     float t_min;
     float T_eps;
@@ -72,16 +77,26 @@ struct HitParams {
 // Load at a wave-uniform address through the constant address space, so the
 // compiler issues a scalar (s_load) instead of a per-lane vector load.  Only
 // for memory that no kernel writes while the loading kernel runs.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 template <class T>
 __device__ inline T uniform_load(const T* p, size_t idx)
 {
     static_assert(sizeof(T) % 4 == 0, "whole dwords only");
-    typedef const uint32_t __attribute__((address_space(4)))* cptr;
-    const cptr src = (cptr)(p + idx);
     T out;
-    uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+    if constexpr (sizeof(T) % 16 == 0) {
+        typedef const u32x4 __attribute__((address_space(4)))* cptr;
+        const cptr src = (cptr)(p + idx);
+        u32x4* dst = reinterpret_cast<u32x4*>(&out);
 #pragma unroll
-    for (size_t i = 0; i < sizeof(T) / 4; ++i) dst[i] = src[i];
+        for (size_t i = 0; i < sizeof(T) / 16; ++i) dst[i] = src[i];
+    } else {
+        typedef const uint32_t __attribute__((address_space(4)))* cptr;
+        const cptr src = (cptr)(p + idx);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+        for (size_t i = 0; i < sizeof(T) / 4; ++i) dst[i] = src[i];
+    }
     return out;
 }
 
@@ -105,6 +120,7 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t stream);
 // ------------------------------------------------------------------------
 hipError_t launch_direction_table(int S, uint64_t seed, int bands, double* d64, double* y64, float* d32,
                                   float* y32, hipStream_t stream);
+hipError_t launch_direction_order(int S, int32_t* order, hipStream_t stream);
 hipError_t launch_build_bvh(const prtgs_gaussians& g, void* bvh, void* ws, unsigned* flags, hipStream_t stream);
 size_t build_workspace_bytes(int n);
 hipError_t launch_leaf_order(const void* bvh, int n, int32_t* order, hipStream_t stream);
@@ -112,15 +128,19 @@ hipError_t launch_leaf_order(const void* bvh, int n, int32_t* order, hipStream_t
 struct TransferArgs {
     const Node* nodes;
     const Prim* prims;
+    const float4* normals;  // leaf order
     const int32_t* order;
     const float* dirs;      // [S][3]
     const float* Y;         // [S][K]
+    const int32_t* dir_order;  // [S] directions in coherent (tile) order
     int S, K, n, first, count, channels;
     HitParams hp;
     float* transfer;        // [n][C][K]
     float* vis;             // [n][S] or null
     float* tdir_sorted;     // [n][K] leaf order, or null
     const float* albedo;    // [n][3] original order (bounce)
+    float4* albedo_sorted;  // [n] leaf order (bounce scratch), or null
+    int G;                  // sources per wave (group split); 1 = fan kernel
     unsigned* flags;
 };
 hipError_t launch_transfer_direct(const TransferArgs& a, hipStream_t stream, unsigned long long* stats = nullptr);

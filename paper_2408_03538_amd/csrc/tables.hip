@@ -104,6 +104,39 @@ __global__ void direction_table_kernel(int S, int nu, int nv, uint64_t seed, int
     }
 }
 
+// Rank of stratum s in a coherent order: strata are grouped into tiles of
+// (up to) 8 z-bands x 8 phi-sectors, tiles in row-major order, row-major
+// inside a tile, so that 64 consecutive directions cover a compact patch.
+__device__ inline int tile_key(int s, int nu, int nv)
+{
+    int a = s / nv, b = s - a * nv;
+    int ta = nu < 8 ? nu : 8;
+    int tb = 64 / ta;
+    if (tb > nv) tb = nv;
+    int ntb = (nv + tb - 1) / tb;
+    int ia = a % ta, ib = b % tb;
+    int within = ia * tb + ib;
+    if (ta == 8 && tb == 8) {   // full tiles in Morton order: aligned runs of 2^k are compact
+        within = 0;
+        for (int bit = 0; bit < 3; ++bit) within |= (((ib >> bit) & 1) << (2 * bit)) | (((ia >> bit) & 1) << (2 * bit + 1));
+    }
+    return ((a / ta) * ntb + (b / tb)) * (ta * tb) + within;
+}
+
+__global__ void direction_order_kernel(int S, int nu, int nv, int32_t* order)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    if (S > 8192) {   // the quadratic ranking below is for table sizes in use; keep large tables in place
+        order[s] = s;
+        return;
+    }
+    int key = tile_key(s, nu, nv);
+    int rank = 0;   // keys are distinct: the rank is the count of smaller keys
+    for (int u = 0; u < S; ++u) rank += tile_key(u, nu, nv) < key;
+    order[rank] = s;
+}
+
 }  // namespace
 
 void stratified_grid(int S, int* nu, int* nv)
@@ -126,6 +159,14 @@ hipError_t launch_direction_table(int S, uint64_t seed, int bands, double* d64, 
     int blocks = (S + threads - 1) / threads;
     hipLaunchKernelGGL(direction_table_kernel, dim3(blocks), dim3(threads), 0, stream, S, nu, nv, seed, bands, d64,
                        y64, d32, y32);
+    return hipGetLastError();
+}
+
+hipError_t launch_direction_order(int S, int32_t* order, hipStream_t stream)
+{
+    int nu, nv;
+    stratified_grid(S, &nu, &nv);
+    hipLaunchKernelGGL(direction_order_kernel, dim3((S + 63) / 64), dim3(64), 0, stream, S, nu, nv, order);
     return hipGetLastError();
 }
 

@@ -53,13 +53,15 @@ def _parse_bvh(buf, n):
     raw = buf.cpu().numpy()
     off_nodes = 256
     off_prims = off_nodes + a256(64 * max(n - 1, 1))
-    off_order = off_prims + a256(64 * n)
+    off_normals = off_prims + a256(64 * n)
+    off_order = off_normals + a256(16 * n)
     nodes_f = raw[off_nodes:off_nodes + 64 * max(n - 1, 1)].view(np.float32).reshape(-1, 16)
     nodes_i = raw[off_nodes:off_nodes + 64 * max(n - 1, 1)].view(np.int32).reshape(-1, 16)
     prims = raw[off_prims:off_prims + 64 * n].view(np.float32).reshape(n, 16)
+    normals = raw[off_normals:off_normals + 16 * n].view(np.float32).reshape(n, 4)
     order = raw[off_order:off_order + 4 * n].view(np.int32)
     hdr = raw[:48].view(np.int32)
-    return hdr, nodes_f, nodes_i, prims, order
+    return hdr, nodes_f, nodes_i, prims, normals, order
 
 
 @pytest.mark.parametrize("gen,n", [("cloud", 1000), ("surface", 5000), ("cloud", 2), ("surface", 777)])
@@ -67,7 +69,7 @@ def test_bvh_structure(prt, gen, n):
     arr = scenegen.random_cloud(n, 5) if gen == "cloud" else scenegen.surface_scene(n, 6)
     sc = prt.Scene.from_arrays(arr)
     bvh = prt.build_bvh(sc, check=True)
-    hdr, nf, ni, prims, order = _parse_bvh(bvh.buffer, n)
+    hdr, nf, ni, prims, normals, order = _parse_bvh(bvh.buffer, n)
     assert hdr[0] == n
     assert sorted(order.tolist()) == list(range(n))
     assert np.array_equal(bvh.leaf_order().cpu().numpy(), order)
@@ -109,7 +111,10 @@ def test_bvh_structure(prt, gen, n):
     # leaf records: centre, opacity and normal of the Gaussian in that leaf
     assert np.allclose(prims[:, 0:3], arr["means"][order], atol=1e-6)
     assert np.allclose(prims[:, 3], arr["opacity"][order], atol=1e-7)
-    assert np.allclose(prims[:, [7, 11, 15]], arr["normals"][order], atol=1e-6)
+    assert np.allclose(normals[:, :3], arr["normals"][order], atol=1e-6)
+    # whitening rows: W^T W is the inverse covariance; w0.w = 1 / min scale
+    s_min = np.exp(arr["log_scales"][order]).min(1)
+    assert np.allclose(prims[:, 7], 1.0 / s_min, rtol=1e-5)
     # Morton order: leaf centres sorted by their 30-bit codes
     lo = arr["means"].astype(np.float32).min(0)
     hi = arr["means"].astype(np.float32).max(0)
