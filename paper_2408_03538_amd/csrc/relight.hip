@@ -79,18 +79,21 @@ __global__ __launch_bounds__(kThreadsF32) void relight_f32_kernel(int n, const f
 }
 
 // ------------------------------------------------------------------ MFMA path
-// GEMM of 16-splat row tiles against column tiles of 16 outputs (b, c) with
+// GEMM of 16-splat row tiles against 16-column tiles of outputs (b, c) with
 // v_mfma_f32_16x16x32_{bf16,f16}.  The 32-deep contraction of one MFMA is
 // [T_c' | T_c'] . [L_hi ; L_lo] for channel c', where L_hi is the light
 // rounded to 16 bits and L_lo the rounded remainder, so the light enters at
 // ~FP32 precision; columns of other channels get zeros (C == 3 needs C such
 // steps).  Lane l holds A[l % 16][8 (l / 16) + 0..7], B[8 (l / 16) + 0..7][l % 16]
-// and D[4 (l / 16) + 0..3][l % 16].  Each of the 4 waves of a block owns MT
-// column tiles, whose B fragments stay in registers; the 16 x 3B output tile
-// of a row tile is contiguous in memory and is staged in LDS for full-width
-// stores.
+// and D[4 (l / 16) + 0..3][l % 16].
+// Work item = (16-row tile, chunk of CT column tiles).  Every wave works on
+// its own items (no block barrier): it keeps the B fragments of one column
+// chunk in registers and walks row tiles; each result tile goes through a
+// wave-private LDS patch so that the 16 rows x 16 CT columns leave in 16-byte
+// stores (each row of the chunk is contiguous in memory).
 
 constexpr int kWavesMfma = 4;
+constexpr int kChunkTiles = 4;   // column tiles per chunk (64 output columns)
 
 template <bool BF>
 struct Frag;
@@ -109,44 +112,48 @@ struct Frag<false> {
     static __device__ inline elem from_float(float x) { return (elem)x; }
 };
 
-template <int K, int C, int MT, bool BF, bool OUT16>
+template <int K, int C, bool BF, bool OUT16>
 __global__ __launch_bounds__(kWavesMfma * kWave) void relight_mfma_kernel(int n, const void* __restrict__ Tv, int B,
                                                                           const float* __restrict__ L,
-                                                                          void* __restrict__ out)
+                                                                          void* __restrict__ out, int waves_per_chunk)
 {
     using F = Frag<BF>;
     using vec = typename F::vec;
     using elem = typename F::elem;
-    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int CT = kChunkTiles;
+    constexpr int kOutBytes = OUT16 ? 2 : 4;
+    constexpr int kRowBytes = CT * 16 * kOutBytes;          // one row of a chunk: 128 or 256 B
+    __shared__ __align__(16) unsigned char stage[kWavesMfma][16 * kRowBytes];
     const elem* T = static_cast<const elem*>(Tv);
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
+    const int wslot = threadIdx.x / kWave;
+    const int gwave = blockIdx.x * kWavesMfma + wslot;
     const int cols = 3 * B;
-    const int ntiles = (cols + 15) / 16;
+    const int nchunks = (cols + 16 * CT - 1) / (16 * CT);
+    const int chunk = gwave % nchunks;
+    const int wave_in_chunk = gwave / nchunks;
+    if (wave_in_chunk >= waves_per_chunk) return;
     const int g = lane / 16;   // k group of the lane's A/B fragment
     const int li = lane % 16;  // row (A) / column (B, D) of the lane
 
-    // B fragments of this wave's column tiles, for every channel step
-    vec bfrag[MT][C];
+    vec bfrag[CT][C];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        int tile = wave + m * kWavesMfma;
-        int col = tile * 16 + li;
-        bool cvalid = tile < ntiles && col < cols;
-        int ch = cvalid ? col % 3 : 0;
+    for (int m = 0; m < CT; ++m) {
+        const int col = (chunk * CT + m) * 16 + li;
+        const bool cvalid = col < cols;
+        const int ch = cvalid ? col % 3 : 0;
 #pragma unroll
         for (int st = 0; st < C; ++st) {
             vec v;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                int k = 8 * g + e;          // 0..31
-                int kk = k & 15;
-                bool lo = k >= 16;
+                const int k = 8 * g + e;   // 0..31
+                const int kk = k & 15;
                 float x = 0.0f;
                 if (cvalid && kk < K && (C == 1 || ch == st)) {
-                    float full = L[(size_t)col * K + kk];
-                    elem hi = F::from_float(full);
-                    x = lo ? (full - (float)hi) : full;
+                    const float full = L[(size_t)col * K + kk];
+                    const elem hi = F::from_float(full);
+                    x = (k >= 16) ? (full - (float)hi) : full;
                 }
                 v[e] = F::from_float(x);
             }
@@ -154,73 +161,74 @@ __global__ __launch_bounds__(kWavesMfma * kWave) void relight_mfma_kernel(int n,
         }
     }
 
-    const size_t row_elems = (size_t)cols;
-    for (int64_t base = (int64_t)blockIdx.x * 16; base < n; base += (int64_t)gridDim.x * 16) {
-        const int64_t row = base + li;
+    unsigned char* my_stage = stage[wslot];
+    const int ntiles_rows = (n + 15) / 16;
+    const int chunk_col0 = chunk * CT * 16;
+    const int chunk_cols = min(CT * 16, cols - chunk_col0);
+    for (int rt = wave_in_chunk; rt < ntiles_rows; rt += waves_per_chunk) {
+        const int64_t row = (int64_t)rt * 16 + li;
         const bool rvalid = row < n;
         vec afrag[C];
 #pragma unroll
         for (int st = 0; st < C; ++st) {
             if (K == 16 && rvalid) {
-                const elem* src = T + ((size_t)row * C + st) * 16 + 8 * (g & 1);
-                afrag[st] = *reinterpret_cast<const vec*>(src);
+                afrag[st] = *reinterpret_cast<const vec*>(T + ((size_t)row * C + st) * 16 + 8 * (g & 1));
             } else {
                 vec v;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    int kk = (8 * g + e) & 15;
+                    const int kk = (8 * g + e) & 15;
                     v[e] = (rvalid && kk < K) ? T[((size_t)row * C + st) * K + kk] : F::from_float(0.0f);
                 }
                 afrag[st] = v;
             }
         }
-        const int nrows = (int)((n - base) < 16 ? (n - base) : 16);
-        __syncthreads();   // previous tile's stores have read the staging area
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            int tile = wave + m * kWavesMfma;
-            if (tile < ntiles) {
-                f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int m = 0; m < CT; ++m) {
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int st = 0; st < C; ++st) acc = F::mma(afrag[st], bfrag[m][st], acc);
-                int col = tile * 16 + li;
-                if (col < cols) {
+            for (int st = 0; st < C; ++st) acc = F::mma(afrag[st], bfrag[m][st], acc);
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        int r = 4 * g + v;
-                        if (OUT16) reinterpret_cast<__half*>(smem)[r * cols + col] = __float2half(acc[v]);
-                        else reinterpret_cast<float*>(smem)[r * cols + col] = acc[v];
-                    }
+            for (int v = 0; v < 4; ++v) {
+                const int r = 4 * g + v;
+                const int c = m * 16 + li;
+                if (OUT16) reinterpret_cast<__half*>(my_stage)[r * CT * 16 + c] = __float2half(acc[v]);
+                else reinterpret_cast<float*>(my_stage)[r * CT * 16 + c] = acc[v];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // 16 rows x kRowBytes, in 16-byte pieces; every row of the chunk is contiguous
+        constexpr int kPiecesPerRow = kRowBytes / 16;
+        const int nrows = (int)min((int64_t)16, (int64_t)n - (int64_t)rt * 16);
+        const size_t row_stride = (size_t)cols * kOutBytes;
+        unsigned char* obase = static_cast<unsigned char*>(out) + (size_t)rt * 16 * row_stride +
+                               (size_t)chunk_col0 * kOutBytes;
+        const bool full_chunk = chunk_cols == CT * 16 && (row_stride % 16) == 0 &&
+                                (reinterpret_cast<uintptr_t>(out) % 16) == 0;
+        if (full_chunk) {
+#pragma unroll
+            for (int pc = lane; pc < 16 * kPiecesPerRow; pc += kWave) {
+                const int r = pc / kPiecesPerRow, piece = pc % kPiecesPerRow;
+                if (r < nrows)
+                    *reinterpret_cast<uint4*>(obase + r * row_stride + piece * 16) =
+                        *reinterpret_cast<const uint4*>(my_stage + r * kRowBytes + piece * 16);
+            }
+        } else {
+            for (int e = lane; e < 16 * chunk_cols; e += kWave) {
+                const int r = e / chunk_cols, c = e % chunk_cols;
+                if (r < nrows) {
+                    if (OUT16)
+                        reinterpret_cast<__half*>(obase + r * row_stride)[c] =
+                            reinterpret_cast<const __half*>(my_stage)[r * CT * 16 + c];
+                    else
+                        reinterpret_cast<float*>(obase + r * row_stride)[c] =
+                            reinterpret_cast<const float*>(my_stage)[r * CT * 16 + c];
                 }
             }
         }
-        __syncthreads();
-        // the tile's rows are one contiguous run of nrows * cols values
-        const size_t total = (size_t)nrows * row_elems;
-        const size_t obase = (size_t)base * row_elems;
-        if (OUT16) {
-            const size_t nvec = total / 8;
-            const uint4* s4 = reinterpret_cast<const uint4*>(smem);
-            __half* o = static_cast<__half*>(out) + obase;
-            if ((reinterpret_cast<uintptr_t>(o) & 15) == 0) {
-                for (size_t e = threadIdx.x; e < nvec; e += blockDim.x) reinterpret_cast<uint4*>(o)[e] = s4[e];
-                for (size_t e = nvec * 8 + threadIdx.x; e < total; e += blockDim.x)
-                    o[e] = reinterpret_cast<const __half*>(smem)[e];
-            } else {
-                for (size_t e = threadIdx.x; e < total; e += blockDim.x) o[e] = reinterpret_cast<const __half*>(smem)[e];
-            }
-        } else {
-            const size_t nvec = total / 4;
-            const float4* s4 = reinterpret_cast<const float4*>(smem);
-            float* o = static_cast<float*>(out) + obase;
-            if ((reinterpret_cast<uintptr_t>(o) & 15) == 0) {
-                for (size_t e = threadIdx.x; e < nvec; e += blockDim.x) reinterpret_cast<float4*>(o)[e] = s4[e];
-                for (size_t e = nvec * 4 + threadIdx.x; e < total; e += blockDim.x)
-                    o[e] = reinterpret_cast<const float*>(smem)[e];
-            } else {
-                for (size_t e = threadIdx.x; e < total; e += blockDim.x) o[e] = reinterpret_cast<const float*>(smem)[e];
-            }
-        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
 }
 
@@ -311,31 +319,25 @@ hipError_t f32_dispatch(int n, const float* T, int B, const float* L, void* out,
     return f32_dispatch_out<K, C, 3>(n, T, B, L, out, out16, stream);
 }
 
-template <int K, int C, int MT, bool BF>
-hipError_t mfma_dispatch_out(int n, const void* T, int B, const float* L, void* out, bool out16, hipStream_t stream)
-{
-    int blocks = (int)((n + 15) / 16);
-    if (blocks > 8192) blocks = 8192;
-    size_t shmem = (size_t)16 * 3 * B * (out16 ? 2 : 4);
-    if (out16)
-        hipLaunchKernelGGL((relight_mfma_kernel<K, C, MT, BF, true>), dim3(blocks), dim3(kWavesMfma * kWave), shmem,
-                           stream, n, T, B, L, out);
-    else
-        hipLaunchKernelGGL((relight_mfma_kernel<K, C, MT, BF, false>), dim3(blocks), dim3(kWavesMfma * kWave), shmem,
-                           stream, n, T, B, L, out);
-    return hipGetLastError();
-}
-
 template <int K, int C, bool BF>
 hipError_t mfma_dispatch(int n, const void* T, int B, const float* L, void* out, bool out16, hipStream_t stream)
 {
-    int ntiles = (3 * B + 15) / 16;
-    int mt = (ntiles + kWavesMfma - 1) / kWavesMfma;
-    if (mt <= 1) return mfma_dispatch_out<K, C, 1, BF>(n, T, B, L, out, out16, stream);
-    if (mt <= 2) return mfma_dispatch_out<K, C, 2, BF>(n, T, B, L, out, out16, stream);
-    if (mt <= 3) return mfma_dispatch_out<K, C, 3, BF>(n, T, B, L, out, out16, stream);
-    if (mt <= 6) return mfma_dispatch_out<K, C, 6, BF>(n, T, B, L, out, out16, stream);
-    return mfma_dispatch_out<K, C, 12, BF>(n, T, B, L, out, out16, stream);
+    const int cols = 3 * B;
+    const int nchunks = (cols + 16 * kChunkTiles - 1) / (16 * kChunkTiles);
+    const int row_tiles = (n + 15) / 16;
+    // about 8 waves per SIMD over 256 CUs, split evenly over the column chunks
+    int waves_per_chunk = (256 * 4 * 8 + nchunks - 1) / nchunks;
+    if (waves_per_chunk > row_tiles) waves_per_chunk = row_tiles;
+    if (waves_per_chunk < 1) waves_per_chunk = 1;
+    const int waves = waves_per_chunk * nchunks;
+    const int blocks = (waves + kWavesMfma - 1) / kWavesMfma;
+    if (out16)
+        hipLaunchKernelGGL((relight_mfma_kernel<K, C, BF, true>), dim3(blocks), dim3(kWavesMfma * kWave), 0, stream, n,
+                           T, B, L, out, waves_per_chunk);
+    else
+        hipLaunchKernelGGL((relight_mfma_kernel<K, C, BF, false>), dim3(blocks), dim3(kWavesMfma * kWave), 0, stream, n,
+                           T, B, L, out, waves_per_chunk);
+    return hipGetLastError();
 }
 
 template <int K, int C>
