@@ -209,6 +209,7 @@ static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1]
  * Eq. 27 as read here).  Returns 1 on a hit, with ambiguity flags. */
 typedef struct {
     double t, alpha;
+    double alpha_if_hit; /* alpha it has, or would have were it a hit */
     int j;
     int amb; /* the hit predicate is within its margin */
 } OraHit;
@@ -252,6 +253,19 @@ static int ora_test(const OraGauss* g, const double* org, const double* w, const
     return hit;
 }
 
+/* The alpha Gaussian g would contribute to the ray org + t w were its hit
+ * predicate true (used for the deviation bounds of ambiguous misses). */
+static double ora_alpha_if_hit(const OraGauss* g, const double* org, const double* w, const double* cut)
+{
+    double rel[3] = {g->mu[0] - org[0], g->mu[1] - org[1], g->mu[2] - org[2]};
+    double sw[3], se[3];
+    matvec3(g->sinv, w, sw);
+    double tt = dot3(rel, sw) / dot3(w, sw);
+    double e[3] = {org[0] + tt * w[0] - g->mu[0], org[1] + tt * w[1] - g->mu[1], org[2] + tt * w[2] - g->mu[2]};
+    matvec3(g->sinv, e, se);
+    return fmin(g->o * exp(-0.5 * dot3(e, se)), cut[4]);
+}
+
 /* Transmittance along one ray through all Gaussians but `self` (Eq. 4's
  * product), with the bounds lo/hi that a different resolution of the
  * ambiguous predicates could give. */
@@ -268,17 +282,7 @@ static double ora_ray_vis(const OraGauss* g, int n, int self, const double* w, c
         if (hit) v *= 1.0 - alpha;
         if (amb) {
             /* the other resolution: hit with the alpha it would have */
-            double d_alpha = alpha;
-            if (!hit) {
-                double rel[3] = {g[j].mu[0] - org[0], g[j].mu[1] - org[1], g[j].mu[2] - org[2]};
-                double sw[3], se[3];
-                matvec3(g[j].sinv, w, sw);
-                double tt = dot3(rel, sw) / dot3(w, sw);
-                double e[3] = {org[0] + tt * w[0] - g[j].mu[0], org[1] + tt * w[1] - g[j].mu[1],
-                               org[2] + tt * w[2] - g[j].mu[2]};
-                matvec3(g[j].sinv, e, se);
-                d_alpha = fmin(g[j].o * exp(-0.5 * dot3(e, se)), cut[4]);
-            }
+            double d_alpha = hit ? alpha : ora_alpha_if_hit(&g[j], org, w, cut);
             v_amb *= 1.0 - d_alpha;
         } else if (hit) {
             v_def *= 1.0 - alpha;
@@ -441,16 +445,18 @@ int ora_bounce(int n, const double* means, const double* quats, const double* lo
                     int hit = ora_test(&g[j], g[i].mu, w, cut, mar, &t, &alpha, &amb);
                     if (amb) amb_ray = 1;
                     if (amb && !hit) {
-                        /* keep it in the list with its would-be alpha, marked, so
-                         * that it enters the deviation bound but not the sum */
+                        /* keep it in the list, marked, with the alpha it would
+                         * have: it enters the deviation bound but not the sum */
                         hits[nh].t = t;
                         hits[nh].alpha = -1.0;
+                        hits[nh].alpha_if_hit = ora_alpha_if_hit(&g[j], g[i].mu, w, cut);
                         hits[nh].j = j;
                         hits[nh].amb = 1;
                         ++nh;
                     } else if (hit) {
                         hits[nh].t = t;
                         hits[nh].alpha = alpha;
+                        hits[nh].alpha_if_hit = alpha;
                         hits[nh].j = j;
                         hits[nh].amb = amb;
                         ++nh;
@@ -463,6 +469,16 @@ int ora_bounce(int n, const double* means, const double* quats, const double* lo
                 int K3 = 3 * K;
                 for (int k = 0; k < K3 && k < 3 * 64; ++k) bound[k] = 0.0;
                 int ended = 0;
+                /* Deviation bound of this ray, in units of max |rho t_dir / pi|
+                 * over its hits.  The blend C = sum_k alpha_k T_k V_k has
+                 * |dC/d alpha_h| <= 2 T_h max|V| (the later weights form a
+                 * partition of at most unity), and T_h at most the product over
+                 * the unambiguous hits in front of h; so each ambiguous hit adds
+                 * 2 alpha_h T_h^def.  Two tied hits a, b swap at a cost of
+                 * 2 alpha_a alpha_b T max|V|.  Where the walk stops may move: the
+                 * tail beyond is below T_eps exp(sum alpha / (1 - alpha)) over the
+                 * ambiguous hits.  Two blends never differ by more than 2. */
+                double T_def = 1.0, T_run = 1.0, run_alpha = 0.0, units = 0.0, A = 0.0;
                 for (int h = 0; h < nh; ++h) {
                     int j = hits[h].j;
                     int row = slot[j];
@@ -474,12 +490,27 @@ int ora_bounce(int n, const double* means, const double* quats, const double* lo
                     const double* td = t_dir + (size_t)row * K;
                     const double* rho = albedo + 3 * (size_t)j;
                     if (mar) {
-                        if (h > 0 && fabs(hits[h].t - hits[h - 1].t) <= mar[4] * (1.0 + fabs(hits[h].t))) amb_ray = 1;
                         for (int ch = 0; ch < 3; ++ch)
                             for (int k = 0; k < K; ++k) {
                                 double m = rho[ch] / ORA_PI * (fabs(td[k]) + (allow_dir ? allow_dir[(size_t)row * K + k] : 0.0));
                                 if (m > bound[ch * K + k]) bound[ch * K + k] = m;
                             }
+                        if (!ended) {
+                            double aa = hits[h].alpha_if_hit;
+                            int tied = h > 0 && fabs(hits[h].t - hits[h - 1].t) <= mar[4] * (1.0 + fabs(hits[h].t));
+                            if (tied) {
+                                amb_ray = 1;
+                                units += 2.0 * aa * run_alpha * T_run;
+                                run_alpha += aa;
+                            } else {
+                                T_run = T_def;
+                                run_alpha = aa;
+                            }
+                            if (hits[h].amb) {
+                                units += 2.0 * aa * T_def;
+                                A += aa / (1.0 - aa);
+                            }
+                        }
                     }
                     if (ended || hits[h].alpha < 0.0) continue;
                     double a = hits[h].alpha;
@@ -493,12 +524,16 @@ int ora_bounce(int n, const double* means, const double* quats, const double* lo
                             for (int k = 0; k < K; ++k)
                                 al[ch * K + k] += wq * cpos * wgt * rho[ch] / ORA_PI * allow_dir[(size_t)row * K + k];
                     T *= 1.0 - a;
+                    if (!hits[h].amb) T_def *= 1.0 - a;
                     if (mar && fabs(T - cut[2]) <= mar[3] * cut[2]) amb_ray = 1;
                     if (T < cut[2]) ended = 1;
                 }
                 if (al && (amb_ray || amb_c)) {
                     double cc = amb_c ? fmax(cpos, mar[0]) : cpos;
-                    for (int k = 0; k < K3; ++k) al[k] += wq * cc * 2.0 * bound[k];
+                    units += 2.0 * (1.0 + mar[3]) * cut[2] * exp(fmin(A, 700.0));
+                    if (amb_c) units += 1.0;   /* the ray may not be traced at all */
+                    if (units > 2.0) units = 2.0;
+                    for (int k = 0; k < K3; ++k) al[k] += wq * cc * units * bound[k];
                 }
             }
         }

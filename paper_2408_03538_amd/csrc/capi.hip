@@ -71,7 +71,7 @@ prtgs_status check_desc(const prtgs_transfer_desc* d)
 }
 
 struct TransferWs {
-    size_t dirs, Y, dir_order, tdir, albedo, total;
+    size_t dirs, Y, dir_order, tdir, albedo, tcut, queue, hits, total;
 };
 
 TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
@@ -89,6 +89,12 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     if (d.bounces) off += align256(sizeof(float) * (size_t)K * (size_t)n);
     w.albedo = off;
     if (d.bounces) off += align256(sizeof(float) * 4 * (size_t)n);
+    w.tcut = off;
+    if (d.bounces) off += align256(sizeof(float) * (size_t)n * (size_t)d.num_dirs);
+    w.queue = off;
+    if (d.bounces) off += 256;
+    w.hits = off;
+    if (d.bounces) off += align256((size_t)bounce_waves(n) * kHitList * 64 * 16);
     w.total = off;
     return w;
 }
@@ -219,7 +225,7 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g, const void* bvh
 
     const BvhLayout L = bvh_layout(n);
     const char* b = static_cast<const char*>(bvh);
-    TransferArgs a;
+    TransferArgs a{};
     a.nodes = reinterpret_cast<const Node*>(b + L.nodes);
     a.prims = reinterpret_cast<const Prim*>(b + L.prims);
     a.normals = reinterpret_cast<const float4*>(b + L.normals);
@@ -239,6 +245,9 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g, const void* bvh
     a.tdir_sorted = d->bounces ? reinterpret_cast<float*>(w + W.tdir) : nullptr;
     a.albedo = g->albedo;
     a.albedo_sorted = d->bounces ? reinterpret_cast<float4*>(w + W.albedo) : nullptr;
+    a.tcut = d->bounces ? reinterpret_cast<float*>(w + W.tcut) : nullptr;
+    a.queue = d->bounces ? reinterpret_cast<unsigned*>(w + W.queue) : nullptr;
+    a.hitlist = d->bounces ? reinterpret_cast<uint4*>(w + W.hits) : nullptr;
     a.G = group_size(count);
     a.flags = flags;
     e = launch_transfer_direct(a, stream);
@@ -281,7 +290,7 @@ prtgs_status prtgs_traversal_stats(const prtgs_gaussians* g, const void* bvh, co
     if (count == 0) return ok();
     const BvhLayout L = bvh_layout(n);
     const char* b = static_cast<const char*>(bvh);
-    TransferArgs a;
+    TransferArgs a{};
     a.nodes = reinterpret_cast<const Node*>(b + L.nodes);
     a.prims = reinterpret_cast<const Prim*>(b + L.prims);
     a.normals = reinterpret_cast<const float4*>(b + L.normals);
@@ -395,7 +404,7 @@ prtgs_status prtgs_transfer_backward(const prtgs_gaussians* g, const void* bvh, 
 
     const BvhLayout L = bvh_layout(n);
     const char* b = static_cast<const char*>(bvh);
-    BackwardArgs a;
+    BackwardArgs a{};
     a.fwd.nodes = reinterpret_cast<const Node*>(b + L.nodes);
     a.fwd.prims = reinterpret_cast<const Prim*>(b + L.prims);
     a.fwd.normals = reinterpret_cast<const float4*>(b + L.normals);

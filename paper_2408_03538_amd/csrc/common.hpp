@@ -12,6 +12,8 @@ namespace prtgs {
 constexpr int kWave = 64;                 // CDNA wavefront width
 constexpr float kBoxSigma = 3.0f;         // BVH boxes enclose the 3-sigma ellipsoid
 constexpr size_t kFlagBytes = 256;        // flag word + padding at the head of a workspace
+constexpr int kHitList = 64;              // bounce: hits kept per ray and round (sorted list)
+constexpr int kBounceWaves = 8192;        // bounce: persistent waves (at most)
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -140,11 +142,20 @@ struct TransferArgs {
     float* tdir_sorted;     // [n][K] leaf order, or null
     const float* albedo;    // [n][3] original order (bounce)
     float4* albedo_sorted;  // [n] leaf order (bounce scratch), or null
+    uint4* hitlist;         // bounce: per-lane sorted hit lists of the persistent
+                            // waves, [wave][kHitList][64] entries {j, t bits, alpha bits, 0}
+    unsigned* queue;        // bounce: work counter (zeroed before the launch)
+    float* tcut;            // [count][S] direction-order position: depth of the
+                            // farthest hit the direct pass used before the ray
+                            // turned opaque (+inf if it never did), or null
     int G;                  // sources per wave (group split); 1 = fan kernel
     unsigned* flags;
 };
 hipError_t launch_transfer_direct(const TransferArgs& a, hipStream_t stream, unsigned long long* stats = nullptr);
 hipError_t launch_transfer_bounce(const TransferArgs& a, hipStream_t stream);
+// Persistent waves of the bounce launch for n sources (any group size): the
+// hit-list scratch holds this many waves.
+inline int bounce_waves(int n) { return n < kBounceWaves ? n : kBounceWaves; }
 
 struct BackwardArgs {
     TransferArgs fwd;

@@ -21,7 +21,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr float kFourPi = 12.566370614359172f;
 constexpr float kInvPi = 0.31830988618379067f;
-constexpr int kBounceBuffer = 16;   // nearest hits kept per ray and round
 
 __device__ inline void kahan_add(float& sum, float& comp, float x)
 {
@@ -111,12 +110,15 @@ __global__ __launch_bounds__(kBlock) void direct_kernel(TransferArgs a, unsigned
         const RayDir d = make_dir(a.dirs[3 * s], a.dirs[3 * s + 1], a.dirs[3 * s + 2]);
         const float c = nrm.x * d.wx + nrm.y * d.wy + nrm.z * d.wz;
         const bool traced = valid && inrange && c > 0.0f;
-        if (!kCount && valid && inrange && !traced && a.vis) a.vis[(size_t)orig * a.S + s] = -1.0f;
+        if (!kCount && valid && inrange && !traced) {
+            if (a.vis) a.vis[(size_t)orig * a.S + s] = -1.0f;
+            if (a.tcut) a.tcut[(size_t)local * a.S + pos] = 0.0f;
+        }
         if (__ballot(traced) == 0ull) continue;
         if (kCount && traced) ++traced_rays;
         const BatchDir bd = batch_dir(d, traced);
         bool live = traced;
-        float T = 1.0f;
+        float T = 1.0f, tfar = 0.0f;
         float tlo = hp.t_min, thi = INFINITY;
         auto leaf = [&](int r, bool box_hit) {
             const Prim p = uniform_load(a.prims, r);
@@ -126,6 +128,7 @@ __global__ __launch_bounds__(kBlock) void direct_kernel(TransferArgs a, unsigned
             HitResult h;
             const bool hit = gaussian_exact(p, q, ox, oy, oz, d, hp, h) & cand;
             T = hit ? T * (1.0f - h.alpha) : T;
+            tfar = hit ? fmaxf(tfar, h.t) : tfar;
             const bool opaque = T < hp.T_eps;
             live = live & !opaque;
             T = opaque ? 0.0f : T;
@@ -136,6 +139,7 @@ __global__ __launch_bounds__(kBlock) void direct_kernel(TransferArgs a, unsigned
 #pragma unroll
             for (int k = 0; k < K; ++k) kahan_add(acc[k], cmp[k], f * a.Y[(size_t)s * K + k]);
             if (a.vis) a.vis[(size_t)orig * a.S + s] = T;
+            if (a.tcut) a.tcut[(size_t)local * a.S + pos] = T == 0.0f ? tfar : INFINITY;
         }
     }
     if (kCount) {
@@ -205,7 +209,10 @@ __global__ __launch_bounds__(kBlock) void direct_fan_kernel(TransferArgs a)
                 pos < seg_n ? nrm.x * a.dirs[3 * s] + nrm.y * a.dirs[3 * s + 1] + nrm.z * a.dirs[3 * s + 2] : 0.0f;
             const uint64_t m = __ballot(c > 0.0f);
             if (c > 0.0f) list[wslot][count + __popcll(m & lt_mask)] = (int16_t)pos;
-            else if (pos < seg_n && a.vis) a.vis[(size_t)orig * a.S + s] = -1.0f;
+            else if (pos < seg_n) {
+                if (a.vis) a.vis[(size_t)orig * a.S + s] = -1.0f;
+                if (a.tcut) a.tcut[(size_t)local * a.S + seg + pos] = 0.0f;
+            }
             count += __popcll(m);
         }
         __builtin_amdgcn_wave_barrier();
@@ -217,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void direct_fan_kernel(TransferArgs a)
             const float c = nrm.x * d.wx + nrm.y * d.wy + nrm.z * d.wz;
             const BatchDir bd = batch_dir(d, traced);
             bool live = traced;
-            float T = 1.0f;
+            float T = 1.0f, tfar = 0.0f;
             float tlo = hp.t_min, thi = INFINITY;
             auto leaf = [&](int r, bool box_hit) {
                 const Prim p = uniform_load(a.prims, r);
@@ -227,6 +234,7 @@ __global__ __launch_bounds__(kBlock) void direct_fan_kernel(TransferArgs a)
                 HitResult h;
                 const bool hit = gaussian_exact(p, q, ox, oy, oz, d, hp, h) & cand;
                 T = hit ? T * (1.0f - h.alpha) : T;
+                tfar = hit ? fmaxf(tfar, h.t) : tfar;
                 const bool opaque = T < hp.T_eps;
                 live = live & !opaque;
                 T = opaque ? 0.0f : T;
@@ -237,6 +245,7 @@ __global__ __launch_bounds__(kBlock) void direct_fan_kernel(TransferArgs a)
 #pragma unroll
                 for (int k = 0; k < K; ++k) kahan_add(acc[k], cmp[k], f * a.Y[(size_t)s * K + k]);
                 if (a.vis) a.vis[(size_t)orig * a.S + s] = T;
+                if (a.tcut) a.tcut[(size_t)local * a.S + seg + list[wslot][idx]] = T == 0.0f ? tfar : INFINITY;
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -263,100 +272,123 @@ __global__ __launch_bounds__(kBlock) void direct_fan_kernel(TransferArgs a)
 // one bounce, group split
 // ---------------------------------------------------------------------------
 
-// Strict order of hits along a ray: by t*, then by leaf rank.
-__device__ inline bool key_less(float ta, int ja, float tb, int jb) { return ta < tb || (ta == tb && ja < jb); }
+// Strict order of hits along a ray, by t* then by leaf rank, as one 64-bit
+// key: t* >= 0, so its bit pattern orders like the value (+ 0 turns -0 into
+// +0).  kNoHit (t = inf) sorts after every hit.
+__device__ inline uint64_t hit_key(float t, int j)
+{
+    return ((uint64_t)__float_as_uint(t + 0.0f) << 32) | (uint32_t)j;
+}
+constexpr uint64_t kNoHit = 0x7f800000ffffffffull;
+__device__ inline float key_t(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ inline int key_j(uint64_t k) { return (int)(uint32_t)k; }
 
 // The hits of each ray are needed front to back (weight alpha_j T_j, T_j the
 // transmittance in front of hit j), up to the one that takes the
-// transmittance below T_eps.  A ray keeps the KB nearest hits beyond the
-// last processed one, sorted in registers (boxes beyond the KB-th nearest so
-// far are culled), blends them in order after the traversal, and repeats
-// from its last hit while the buffer came back full and transparent.
-template <int K, int KB>
-__global__ __launch_bounds__(kBlock) void bounce_kernel(TransferArgs a)
+// transmittance below T_eps.  Each lane keeps the kHitList nearest hits of
+// its ray beyond the last blended one in a sorted list of its own in device
+// memory (insertion from the back: the traversal meets hits roughly front to
+// back, so few entries move), culls boxes beyond the last entry of a full
+// list and beyond the depth the direct pass needed, blends the list in order
+// after the traversal, and traverses again from its last hit only while the
+// list came back full and still transparent.  The launch is persistent: a
+// fixed set of waves takes groups of sources from a counter, so the lists
+// are sized by the waves, not by the scene.
+template <int K>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void bounce_kernel(TransferArgs a)
 {
+    constexpr int M = kHitList;
     const int lane = threadIdx.x & (kWave - 1);
     const int G = a.G;
     const int D = kWave / G;
-    const int gwave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-    const int local = gwave * G + lane / D;
-    const bool valid = local < a.count;
-    const int rank = a.first + (valid ? local : 0);
-    const float4 mo = a.prims[rank].mo;
-    const float ox = mo.x, oy = mo.y, oz = mo.z;
-    const float4 nrm = a.normals[rank];
-    const int orig = valid ? a.order[rank] : 0;
+    const int wslot = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+    uint4* const list = a.hitlist + (size_t)wslot * M * kWave + lane;   // entry q at list[q * kWave]
+    const int groups = (a.count + G - 1) / G;
     const HitParams hp = a.hp;
+    // Each full round consumes M hits of at most n - 1, hence the cap.
+    const int max_rounds = a.n / M + 2;
 
-    float acc[3][K];
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch)
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc[ch][k] = 0.0f;
+    for (;;) {
+        int grp = 0;
+        if (lane == 0) grp = (int)atomicAdd(a.queue, 1u);
+        grp = __builtin_amdgcn_readfirstlane(grp);
+        if (grp >= groups) break;   // uniform: every wave leaves once the counter passes the last group
 
-    for (int b0 = 0; b0 < a.S; b0 += D) {
-        const int pos = b0 + (lane % D);
-        const bool inrange = pos < a.S;
-        const int s = inrange ? a.dir_order[pos] : 0;
-        const RayDir d = make_dir(a.dirs[3 * s], a.dirs[3 * s + 1], a.dirs[3 * s + 2]);
-        const float c = nrm.x * d.wx + nrm.y * d.wy + nrm.z * d.wz;
-        bool pending = valid && inrange && c > 0.0f;
-        if (__ballot(pending) == 0ull) continue;
-        const BatchDir bd = batch_dir(d, pending);
-        const float wc = c * kInvPi;
-        float T = 1.0f;
-        float t_last = -INFINITY;
-        int j_last = -1;
-        // Each full round consumes KB hits of at most n - 1, hence the cap.
-        int rounds = a.n / KB + 2;
-        while (__ballot(pending) != 0ull) {
-            if (--rounds < 0) {
-                raise_flag(a.flags, PRTGS_FLAG_BAD_TREE);
-                break;
-            }
-            float bt[KB], ba[KB];
-            int bj[KB];
+        const int local = grp * G + lane / D;
+        const bool valid = local < a.count;
+        const int rank = a.first + (valid ? local : 0);
+        const float4 mo = a.prims[rank].mo;
+        const float ox = mo.x, oy = mo.y, oz = mo.z;
+        const float4 nrm = a.normals[rank];
+        const int orig = valid ? a.order[rank] : 0;
+
+        float acc[3][K];
 #pragma unroll
-            for (int q = 0; q < KB; ++q) {
-                bt[q] = INFINITY;
-                bj[q] = 0x7fffffff;
-                ba[q] = 0.0f;
-            }
-            bool live = pending;
-            float tlo = fmaxf(hp.t_min, t_last), thi = INFINITY;
-            auto leaf = [&](int r, bool box_hit) {
-                const Prim p = uniform_load(a.prims, r);
-                const PreHit q = gaussian_pre(p, ox, oy, oz, d, hp);
-                const bool cand = q.maybe & box_hit & live & (r != rank);
-                if (__ballot(cand) == 0ull) return;
-                HitResult h;
-                const bool hit = gaussian_exact(p, q, ox, oy, oz, d, hp, h) & cand;
-                if (hit && key_less(t_last, j_last, h.t, r) && key_less(h.t, r, bt[KB - 1], bj[KB - 1])) {
-                    float ct = h.t, ca = h.alpha;
-                    int cj = r;
+        for (int ch = 0; ch < 3; ++ch)
 #pragma unroll
-                    for (int q2 = 0; q2 < KB; ++q2) {
-                        const bool lt = key_less(ct, cj, bt[q2], bj[q2]);
-                        const float tt = bt[q2], ta = ba[q2];
-                        const int tj = bj[q2];
-                        bt[q2] = lt ? ct : tt;
-                        bj[q2] = lt ? cj : tj;
-                        ba[q2] = lt ? ca : ta;
-                        ct = lt ? tt : ct;
-                        cj = lt ? tj : cj;
-                        ca = lt ? ta : ca;
-                    }
-                    thi = bt[KB - 1];   // beyond the KB-th nearest nothing is needed this round
+            for (int k = 0; k < K; ++k) acc[ch][k] = 0.0f;
+
+        for (int b0 = 0; b0 < a.S; b0 += D) {
+            const int pos = b0 + (lane % D);
+            const bool inrange = pos < a.S;
+            const int s = inrange ? a.dir_order[pos] : 0;
+            const RayDir d = make_dir(a.dirs[3 * s], a.dirs[3 * s + 1], a.dirs[3 * s + 2]);
+            const float c = nrm.x * d.wx + nrm.y * d.wy + nrm.z * d.wz;
+            bool pending = valid && inrange && c > 0.0f;
+            if (__ballot(pending) == 0ull) continue;
+            const BatchDir bd = batch_dir(d, pending);
+            const float wc = c * kInvPi;
+            // No hit beyond tc can carry weight: the direct pass saw the
+            // transmittance fall below T_eps using hits no farther than tc.
+            const float tc = pending ? a.tcut[(size_t)local * a.S + pos] : 0.0f;
+            float T = 1.0f;
+            bool started = false;
+            uint64_t k_last = 0;   // key of the last blended hit (once started)
+            int rounds = 0;
+            while (__ballot(pending) != 0ull) {
+                if (pending && ++rounds > max_rounds) {
+                    raise_flag(a.flags, PRTGS_FLAG_BAD_TREE);
+                    pending = false;
+                    continue;
                 }
-            };
-            traverse_batch<false>(a, d, bd, ox, oy, oz, live, tlo, thi, leaf, (RayCounts*)nullptr);
-            if (pending) {
-                int used = 0;
-#pragma unroll
-                for (int q = 0; q < KB; ++q) {
-                    if (bt[q] < INFINITY && pending) {
-                        const int r = bj[q];
-                        const float w = ba[q] * T * wc;
+                int cnt = 0;
+                uint64_t k_end = kNoHit;   // key of the last entry of a full list
+                bool live = pending;
+                float tlo = started ? fmaxf(hp.t_min, key_t(k_last)) : hp.t_min, thi = tc;
+                auto leaf = [&](int r, bool box_hit) {
+                    const Prim p = uniform_load(a.prims, r);
+                    const PreHit q = gaussian_pre(p, ox, oy, oz, d, hp);
+                    const bool cand = q.maybe & box_hit & live & (r != rank);
+                    if (__ballot(cand) == 0ull) return;
+                    HitResult h;
+                    const bool hit = gaussian_exact(p, q, ox, oy, oz, d, hp, h) & cand;
+                    const uint64_t key = hit_key(h.t, r);
+                    const bool ins = hit & (h.t <= tc) & (!started | (key > k_last)) & (key < k_end);
+                    if (ins) {
+                        int i = cnt < M ? cnt : M - 1;   // a full list drops its last entry
+                        while (i > 0) {
+                            const uint4 e = list[(i - 1) * kWave];
+                            if ((((uint64_t)e.y << 32) | e.x) < key) break;
+                            list[i * kWave] = e;
+                            --i;
+                        }
+                        list[i * kWave] = make_uint4((uint32_t)key, (uint32_t)(key >> 32), __float_as_uint(h.alpha), 0u);
+                        if (cnt < M) ++cnt;
+                        if (cnt == M) {
+                            const uint4 e = list[(M - 1) * kWave];
+                            k_end = ((uint64_t)e.y << 32) | e.x;
+                            thi = fminf(thi, key_t(k_end));   // nothing beyond the M-th nearest this round
+                        }
+                    }
+                };
+                traverse_batch<false>(a, d, bd, ox, oy, oz, live, tlo, thi, leaf, (RayCounts*)nullptr);
+                if (pending) {
+                    bool done = false;
+                    for (int q = 0; q < cnt && !done; ++q) {
+                        const uint4 e = list[q * kWave];
+                        const int r = (int)e.x;
+                        const float al = __uint_as_float(e.z);
+                        const float w = al * T * wc;
                         const float4 rho = a.albedo_sorted[r];
                         float tv[K];
                         if constexpr (K % 4 == 0) {
@@ -380,29 +412,28 @@ __global__ __launch_bounds__(kBlock) void bounce_kernel(TransferArgs a)
                             acc[1][k] = fmaf(r1, tv[k], acc[1][k]);
                             acc[2][k] = fmaf(r2, tv[k], acc[2][k]);
                         }
-                        T *= 1.0f - ba[q];
-                        t_last = bt[q];
-                        j_last = r;
-                        ++used;
-                        if (T < hp.T_eps) pending = false;
+                        T *= 1.0f - al;
+                        k_last = ((uint64_t)e.y << 32) | e.x;
+                        started = true;
+                        if (T < hp.T_eps) done = true;
                     }
+                    // more hits may lie beyond a full, still transparent list
+                    if (done || cnt < M) pending = false;
                 }
-                // more hits may lie beyond a full, still transparent buffer
-                if (used < KB) pending = false;
             }
         }
-    }
-    const float scale = kFourPi / (float)a.S;
+        const float scale = kFourPi / (float)a.S;
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch)
+        for (int ch = 0; ch < 3; ++ch)
 #pragma unroll
-        for (int k = 0; k < K; ++k) acc[ch][k] = segment_sum(acc[ch][k], D) * scale;
-    if (valid && (lane % D) == 0) {
+            for (int k = 0; k < K; ++k) acc[ch][k] = segment_sum(acc[ch][k], D) * scale;
+        if (valid && (lane % D) == 0) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float* out = a.transfer + ((size_t)orig * 3 + ch) * K;
+            for (int ch = 0; ch < 3; ++ch) {
+                float* out = a.transfer + ((size_t)orig * 3 + ch) * K;
 #pragma unroll
-            for (int k = 0; k < K; ++k) out[k] += acc[ch][k];
+                for (int k = 0; k < K; ++k) out[k] += acc[ch][k];
+            }
         }
     }
 }
@@ -434,7 +465,12 @@ hipError_t launch_direct_k(const TransferArgs& a, unsigned long long* stats, hip
 template <int K>
 hipError_t launch_bounce_k(const TransferArgs& a, hipStream_t stream)
 {
-    hipLaunchKernelGGL((bounce_kernel<K, kBounceBuffer>), dim3(group_blocks(a.count, a.G)), dim3(kBlock), 0, stream, a);
+    hipError_t e = fill_u32(a.queue, 0u, 1, stream);
+    if (e != hipSuccess) return e;
+    const int groups = (a.count + a.G - 1) / a.G;
+    const int waves = groups < bounce_waves(a.n) ? groups : bounce_waves(a.n);   // the hit lists hold this many
+    hipLaunchKernelGGL(bounce_kernel<K>, dim3((waves + kBlock / kWave - 1) / (kBlock / kWave)), dim3(kBlock), 0,
+                       stream, a);
     return hipGetLastError();
 }
 

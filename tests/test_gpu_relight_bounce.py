@@ -39,6 +39,45 @@ def test_bounce_parity_sampled(prt, oracle_mod, S, bands):
     print(f"bounce max |dt| = {err:.2e}, max |t_ind| = {np.abs(ref['t_ind']).max():.3f}")
 
 
+def test_bounce_many_faint_hits(prt, oracle_mod):
+    """A crowded, faint cloud: rays meet hundreds of Gaussians before the
+    transmittance falls below T_eps (or never do), so each ray needs several
+    rounds of the 64-entry hit list."""
+    scene = scenegen.random_cloud(1500, 23)
+    scene["means"] *= 0.3
+    scene["opacity"] *= 0.04
+    scene = as_f32(scene)
+    n = scene["means"].shape[0]
+    S, bands = 32, 3
+    # hits along one ray (3-sigma ellipsoids crossed ahead of the origin)
+    o, w = scene["means"][0].astype(np.float64), np.array([0.6, 0.0, 0.8])
+    R = np.stack([_rot(q) for q in scene["quats"].astype(np.float64)])
+    inv_s2 = np.exp(-2.0 * scene["log_scales"].astype(np.float64))
+    Ainv = np.einsum("nij,nj,nkj->nik", R, inv_s2, R)
+    dx = scene["means"] - o
+    a = np.einsum("i,nij,j->n", w, Ainv, w)
+    b = np.einsum("i,nij,nj->n", w, Ainv, dx)
+    c = np.einsum("ni,nij,nj->n", dx, Ainv, dx)
+    d2 = c - b * b / a
+    assert ((d2 < 9.0) & (b / a > 0)).sum() > 64
+    params = prt.TransferParams(num_dirs=S, sh_bands=bands, bounces=1)
+    sc = prt.Scene.from_arrays(scene)
+    bvh = prt.build_bvh(sc, check=True)
+    t = prt.precompute_transfer(sc, bvh, params, check=True).cpu().numpy()
+    src = np.random.default_rng(4).choice(n, 60, replace=False)
+    ref = oracle_mod.full_transfer(scene, S, bands, 1, sources=src, want_allow=True)
+    err = assert_transfer_parity(t[src], ref["t"], ref["allow"], what="bounce transfer")
+    assert np.abs(ref["t_ind"]).max() > 1e-2
+    print(f"faint cloud: bounce max |dt| = {err:.2e}, max |t_ind| = {np.abs(ref['t_ind']).max():.3f}")
+
+
+def _rot(q):
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
 def test_bounce_zero_albedo_is_direct(prt):
     import torch
     scene = as_f32(_small_million_like(5))

@@ -290,6 +290,29 @@ def test_allowance_is_rare_and_nonnegative(oracle_mod):
 # bounce (Eq. 20-22, 30-33 with the depth-ordered alpha blend)
 # --------------------------------------------------------------------------
 
+def test_allowance_covers_threshold_perturbations(oracle_mod):
+    """The deviation bound must cover every other resolution of the
+    near-threshold predicates: moving the 3-sigma cut and T_eps inside wide
+    margins changes direct and bounce transfers by no more than it.  A faint,
+    crowded cloud gives hundreds of hits per ray, many of them ambiguous."""
+    sc = scenegen.random_cloud(700, 31)
+    sc["means"] *= 0.3
+    sc["opacity"] *= 0.05
+    margins = (1e-6, 0.02, 3e-6, 0.1, 1e-5)
+    src = np.arange(0, 700, 7)
+    base = oracle_mod.full_transfer(sc, 32, 3, 1, sources=src, want_allow=True, margins=margins)
+    moved = 0.0
+    for cut in (dict(sigma_cut=3.0 * (1 + 1e-3)), dict(sigma_cut=3.0 * (1 - 1e-3)),
+                dict(T_eps=1e-4 * 1.05), dict(T_eps=1e-4 * 0.95)):
+        var = oracle_mod.full_transfer(sc, 32, 3, 1, sources=src, cut=cut, margins=margins)
+        diff = np.abs(var["t"] - base["t"])
+        assert (diff <= base["allow"] + 1e-12).all(), (cut, (diff - base["allow"]).max())
+        moved = max(moved, diff.max())
+    assert moved > 1e-6
+    # the bound stays informative: well below the transfer's own size
+    assert np.median(base["allow"]) < 1e-2 * np.abs(base["t"]).max()
+
+
 def test_bounce_partition_of_unity(oracle_mod):
     """With t_dir = e_0 for every hit and rho = pi, the bounce term of a ray
     is c (sum_j alpha_j T_j) = c (1 - T_end) (telescoping)."""
