@@ -150,7 +150,8 @@ prtgs_status prtgs_bvh_leaf_order(const void* bvh, int32_t n, int32_t* order /* 
 /* bounces == 1 the range must be the whole scene).  vis (may be NULL):     */
 /* [n][S] visibility of every ray of the selected sources, -1 for rays with */
 /* c <= 0 (not traced).  ws: prtgs_transfer_workspace_bytes (with a       */
-/* bounce it holds 4 n S bytes of per-ray cut depths, 2 GiB at 1M x 512).   */
+/* bounce it also holds 4 n S bytes of per-ray cut depths, 2 GiB at 1M x    */
+/* 512, and per-lane hit lists of min(n, 4096) waves, 768 MiB).             */
 /* ---------------------------------------------------------------------- */
 size_t prtgs_transfer_workspace_bytes(const prtgs_transfer_desc* d /* host */, int32_t n);
 prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g /* host */, const void* bvh,

@@ -71,7 +71,7 @@ prtgs_status check_desc(const prtgs_transfer_desc* d)
 }
 
 struct TransferWs {
-    size_t dirs, Y, dir_order, tdir, albedo, tcut, queue, hits, total;
+    size_t dirs, Y, dir_order, tdir, albedo, tcut, queue, hitkey, hitalpha, total;
 };
 
 TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
@@ -93,8 +93,10 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     if (d.bounces) off += align256(sizeof(float) * (size_t)n * (size_t)d.num_dirs);
     w.queue = off;
     if (d.bounces) off += 256;
-    w.hits = off;
-    if (d.bounces) off += align256((size_t)bounce_waves(n) * kHitList * 64 * 16);
+    w.hitkey = off;
+    if (d.bounces) off += align256((size_t)bounce_waves(n) * kHitList * 64 * 8);
+    w.hitalpha = off;
+    if (d.bounces) off += align256((size_t)bounce_waves(n) * kHitList * 64 * 4);
     w.total = off;
     return w;
 }
@@ -247,7 +249,8 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g, const void* bvh
     a.albedo_sorted = d->bounces ? reinterpret_cast<float4*>(w + W.albedo) : nullptr;
     a.tcut = d->bounces ? reinterpret_cast<float*>(w + W.tcut) : nullptr;
     a.queue = d->bounces ? reinterpret_cast<unsigned*>(w + W.queue) : nullptr;
-    a.hitlist = d->bounces ? reinterpret_cast<uint4*>(w + W.hits) : nullptr;
+    a.hitkey = d->bounces ? reinterpret_cast<uint64_t*>(w + W.hitkey) : nullptr;
+    a.hitalpha = d->bounces ? reinterpret_cast<float*>(w + W.hitalpha) : nullptr;
     a.G = group_size(count);
     a.flags = flags;
     e = launch_transfer_direct(a, stream);

@@ -12,8 +12,8 @@ namespace prtgs {
 constexpr int kWave = 64;                 // CDNA wavefront width
 constexpr float kBoxSigma = 3.0f;         // BVH boxes enclose the 3-sigma ellipsoid
 constexpr size_t kFlagBytes = 256;        // flag word + padding at the head of a workspace
-constexpr int kHitList = 64;              // bounce: hits kept per ray and round (sorted list)
-constexpr int kBounceWaves = 8192;        // bounce: persistent waves (at most)
+constexpr int kHitList = 256;             // bounce: hits listed per ray and round
+constexpr int kBounceWaves = 4096;        // bounce: persistent waves (at most)
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -142,8 +142,8 @@ struct TransferArgs {
     float* tdir_sorted;     // [n][K] leaf order, or null
     const float* albedo;    // [n][3] original order (bounce)
     float4* albedo_sorted;  // [n] leaf order (bounce scratch), or null
-    uint4* hitlist;         // bounce: per-lane sorted hit lists of the persistent
-                            // waves, [wave][kHitList][64] entries {j, t bits, alpha bits, 0}
+    uint64_t* hitkey;       // bounce: per-lane hit lists of the persistent waves,
+    float* hitalpha;        // [wave][kHitList][64] keys (t bits, leaf rank) and alphas
     unsigned* queue;        // bounce: work counter (zeroed before the launch)
     float* tcut;            // [count][S] direction-order position: depth of the
                             // farthest hit the direct pass used before the ray

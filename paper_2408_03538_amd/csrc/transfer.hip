@@ -285,28 +285,35 @@ __device__ inline int key_j(uint64_t k) { return (int)(uint32_t)k; }
 
 // The hits of each ray are needed front to back (weight alpha_j T_j, T_j the
 // transmittance in front of hit j), up to the one that takes the
-// transmittance below T_eps.  Each lane keeps the kHitList nearest hits of
-// its ray beyond the last blended one in a sorted list of its own in device
-// memory (insertion from the back: the traversal meets hits roughly front to
-// back, so few entries move), culls boxes beyond the last entry of a full
-// list and beyond the depth the direct pass needed, blends the list in order
-// after the traversal, and traverses again from its last hit only while the
-// list came back full and still transparent.  The launch is persistent: a
-// fixed set of waves takes groups of sources from a counter, so the lists
-// are sized by the waves, not by the scene.
+// transmittance below T_eps.  The traversal appends every hit beyond the last
+// blended one and no farther than the depth the direct pass needed to a list
+// of the lane's own in device memory, unsorted (the traversal meets them in
+// no useful order).  Afterwards the lane blends the list nearest first,
+// kBlend hits at a time: one pass over the list (coalesced across the wave)
+// keeps the kBlend nearest unblended keys in a sorted register buffer.  A
+// list that fills up is compacted around the mean depth of its hits: those
+// beyond it are dropped and every later hit beyond it is refused (k_over), so
+// the list stays complete in front of k_over; the lane blends it and, if
+// still transparent, traverses again from its last hit.  The launch is
+// persistent: a fixed set of waves takes groups of sources from a counter,
+// so the lists are sized by the waves, not the scene.
+constexpr int kBlend = 8;   // hits selected per pass over the list
+constexpr int kScan = 8;    // list entries loaded together
+
 template <int K>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void bounce_kernel(TransferArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void bounce_kernel(TransferArgs a)
 {
     constexpr int M = kHitList;
     const int lane = threadIdx.x & (kWave - 1);
     const int G = a.G;
     const int D = kWave / G;
     const int wslot = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-    uint4* const list = a.hitlist + (size_t)wslot * M * kWave + lane;   // entry q at list[q * kWave]
+    uint64_t* const lkey = a.hitkey + (size_t)wslot * M * kWave + lane;   // entry q at [q * kWave]
+    float* const lalpha = a.hitalpha + (size_t)wslot * M * kWave + lane;
     const int groups = (a.count + G - 1) / G;
     const HitParams hp = a.hp;
-    // Each full round consumes M hits of at most n - 1, hence the cap.
-    const int max_rounds = a.n / M + 2;
+    // Each traversal blends at least one of at most n - 1 hits, hence the cap.
+    const int max_rounds = a.n + 1;
 
     for (;;) {
         int grp = 0;
@@ -321,6 +328,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const float ox = mo.x, oy = mo.y, oz = mo.z;
         const float4 nrm = a.normals[rank];
         const int orig = valid ? a.order[rank] : 0;
+        const float scale = kFourPi / (float)a.S;
 
         float acc[3][K];
 #pragma unroll
@@ -346,15 +354,52 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             uint64_t k_last = 0;   // key of the last blended hit (once started)
             int rounds = 0;
             while (__ballot(pending) != 0ull) {
-                if (pending && ++rounds > max_rounds) {
+                // a traversal that ran out of its budget flagged the tree: stop
+                if (pending && (++rounds > max_rounds ||
+                                (__atomic_load_n(a.flags, __ATOMIC_RELAXED) & PRTGS_FLAG_BAD_TREE))) {
                     raise_flag(a.flags, PRTGS_FLAG_BAD_TREE);
                     pending = false;
                     continue;
                 }
                 int cnt = 0;
-                uint64_t k_end = kNoHit;   // key of the last entry of a full list
+                float sum_t = 0.0f;         // of the listed hits (compaction pivot)
+                uint64_t k_over = kNoHit;   // hits from here on wait for the next round
                 bool live = pending;
                 float tlo = started ? fmaxf(hp.t_min, key_t(k_last)) : hp.t_min, thi = tc;
+                // Full list: keep the hits in front of their mean depth (at least
+                // one goes: if rounding keeps them all, the farthest).
+                auto compact = [&]() {
+                    const uint64_t pivot = hit_key(sum_t / (float)cnt, 0);
+                    if (pivot < k_over) k_over = pivot;
+                    int kept = 0;
+                    float kept_sum = 0.0f;
+                    uint64_t kmax = 0;
+                    int imax = 0;
+                    for (int q = 0; q < cnt; ++q) {
+                        const uint64_t k = lkey[q * kWave];
+                        const float al = lalpha[q * kWave];
+                        if (k < k_over) {
+                            lkey[kept * kWave] = k;
+                            lalpha[kept * kWave] = al;
+                            if (k > kmax) {
+                                kmax = k;
+                                imax = kept;
+                            }
+                            kept_sum += key_t(k);
+                            ++kept;
+                        }
+                    }
+                    if (kept == cnt) {   // drop the farthest: move the last entry into its slot
+                        k_over = kmax;
+                        kept_sum -= key_t(kmax);
+                        --kept;
+                        lkey[imax * kWave] = lkey[kept * kWave];
+                        lalpha[imax * kWave] = lalpha[kept * kWave];
+                    }
+                    cnt = kept;
+                    sum_t = kept_sum;
+                    thi = fminf(thi, key_t(k_over));
+                };
                 auto leaf = [&](int r, bool box_hit) {
                     const Prim p = uniform_load(a.prims, r);
                     const PreHit q = gaussian_pre(p, ox, oy, oz, d, hp);
@@ -363,76 +408,121 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     HitResult h;
                     const bool hit = gaussian_exact(p, q, ox, oy, oz, d, hp, h) & cand;
                     const uint64_t key = hit_key(h.t, r);
-                    const bool ins = hit & (h.t <= tc) & (!started | (key > k_last)) & (key < k_end);
+                    const bool ins = hit & (h.t <= tc) & (!started | (key > k_last)) & (key < k_over);
                     if (ins) {
-                        int i = cnt < M ? cnt : M - 1;   // a full list drops its last entry
-                        while (i > 0) {
-                            const uint4 e = list[(i - 1) * kWave];
-                            if ((((uint64_t)e.y << 32) | e.x) < key) break;
-                            list[i * kWave] = e;
-                            --i;
-                        }
-                        list[i * kWave] = make_uint4((uint32_t)key, (uint32_t)(key >> 32), __float_as_uint(h.alpha), 0u);
-                        if (cnt < M) ++cnt;
-                        if (cnt == M) {
-                            const uint4 e = list[(M - 1) * kWave];
-                            k_end = ((uint64_t)e.y << 32) | e.x;
-                            thi = fminf(thi, key_t(k_end));   // nothing beyond the M-th nearest this round
+                        if (cnt == M) compact();
+                        if (key < k_over) {
+                            lkey[cnt * kWave] = key;
+                            lalpha[cnt * kWave] = h.alpha;
+                            sum_t += h.t;
+                            ++cnt;
                         }
                     }
                 };
                 traverse_batch<false>(a, d, bd, ox, oy, oz, live, tlo, thi, leaf, (RayCounts*)nullptr);
-                if (pending) {
-                    bool done = false;
-                    for (int q = 0; q < cnt && !done; ++q) {
-                        const uint4 e = list[q * kWave];
-                        const int r = (int)e.x;
-                        const float al = __uint_as_float(e.z);
-                        const float w = al * T * wc;
-                        const float4 rho = a.albedo_sorted[r];
-                        float tv[K];
-                        if constexpr (K % 4 == 0) {
-                            const float4* td = reinterpret_cast<const float4*>(a.tdir_sorted + (size_t)r * K);
+
+                int maxcnt = pending ? cnt : 0;
+                for (int off = 32; off >= 1; off >>= 1) maxcnt = max(maxcnt, __shfl_xor(maxcnt, off, kWave));
+                bool done = false;
+                bool more = pending && cnt > 0;   // listed hits left to blend
+                while (__ballot(more) != 0ull) {
+                    uint64_t bk[kBlend];
+                    float ba[kBlend];
 #pragma unroll
-                            for (int k4 = 0; k4 < K / 4; ++k4) {
-                                const float4 v = td[k4];
-                                tv[4 * k4] = v.x;
-                                tv[4 * k4 + 1] = v.y;
-                                tv[4 * k4 + 2] = v.z;
-                                tv[4 * k4 + 3] = v.w;
-                            }
-                        } else {
-#pragma unroll
-                            for (int k = 0; k < K; ++k) tv[k] = a.tdir_sorted[(size_t)r * K + k];
-                        }
-                        const float r0 = rho.x * w, r1 = rho.y * w, r2 = rho.z * w;
-#pragma unroll
-                        for (int k = 0; k < K; ++k) {
-                            acc[0][k] = fmaf(r0, tv[k], acc[0][k]);
-                            acc[1][k] = fmaf(r1, tv[k], acc[1][k]);
-                            acc[2][k] = fmaf(r2, tv[k], acc[2][k]);
-                        }
-                        T *= 1.0f - al;
-                        k_last = ((uint64_t)e.y << 32) | e.x;
-                        started = true;
-                        if (T < hp.T_eps) done = true;
+                    for (int q = 0; q < kBlend; ++q) {
+                        bk[q] = kNoHit;
+                        ba[q] = 0.0f;
                     }
-                    // more hits may lie beyond a full, still transparent list
-                    if (done || cnt < M) pending = false;
+                    for (int q0 = 0; q0 < maxcnt; q0 += kScan) {
+                        // kScan entries' loads in flight together
+                        uint64_t kk[kScan];
+                        float aa[kScan];
+#pragma unroll
+                        for (int u = 0; u < kScan; ++u) {
+                            const int q = q0 + u;
+                            const bool inl = more && q < cnt;
+                            kk[u] = inl ? lkey[q * kWave] : kNoHit;
+                            aa[u] = inl ? lalpha[q * kWave] : 0.0f;
+                        }
+#pragma unroll
+                        for (int u = 0; u < kScan; ++u) {
+                            const uint64_t k = kk[u];
+                            const bool sel = (k != kNoHit) & (!started | (k > k_last)) & (k < k_over) &
+                                             (k < bk[kBlend - 1]);
+                            if (__ballot(sel) != 0ull) {
+                                // sorted insertion; lanes without a key carry kNoHit
+                                uint64_t ck = sel ? k : kNoHit;
+                                float ca = aa[u];
+#pragma unroll
+                                for (int q2 = 0; q2 < kBlend; ++q2) {
+                                    const bool lt = ck < bk[q2];
+                                    const uint64_t tk = bk[q2];
+                                    const float ta = ba[q2];
+                                    bk[q2] = lt ? ck : tk;
+                                    ba[q2] = lt ? ca : ta;
+                                    ck = lt ? tk : ck;
+                                    ca = lt ? ta : ca;
+                                }
+                            }
+                        }
+                    }
+                    int got = 0;
+#pragma unroll
+                    for (int q = 0; q < kBlend; ++q) {
+                        // one hit's loads at a time: hoisting all of them would
+                        // hold kBlend (K + 4) registers at once
+                        asm volatile("" ::: "memory");
+                        if (more && !done && bk[q] != kNoHit) {
+                            const int r = key_j(bk[q]);
+                            const float w = ba[q] * T * wc;
+                            const float4 rho = a.albedo_sorted[r];
+                            float tv[K];
+                            if constexpr (K % 4 == 0) {
+                                const float4* td = reinterpret_cast<const float4*>(a.tdir_sorted + (size_t)r * K);
+#pragma unroll
+                                for (int k4 = 0; k4 < K / 4; ++k4) {
+                                    const float4 v = td[k4];
+                                    tv[4 * k4] = v.x;
+                                    tv[4 * k4 + 1] = v.y;
+                                    tv[4 * k4 + 2] = v.z;
+                                    tv[4 * k4 + 3] = v.w;
+                                }
+                            } else {
+#pragma unroll
+                                for (int k = 0; k < K; ++k) tv[k] = a.tdir_sorted[(size_t)r * K + k];
+                            }
+                            const float r0 = rho.x * w, r1 = rho.y * w, r2 = rho.z * w;
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                acc[0][k] = fmaf(r0, tv[k], acc[0][k]);
+                                acc[1][k] = fmaf(r1, tv[k], acc[1][k]);
+                                acc[2][k] = fmaf(r2, tv[k], acc[2][k]);
+                            }
+                            T *= 1.0f - ba[q];
+                            k_last = bk[q];
+                            started = true;
+                            ++got;
+                            if (T < hp.T_eps) done = true;
+                        }
+                    }
+                    // a buffer that came back short held the last listed hits
+                    if (done || got < kBlend) more = false;
                 }
-            }
-        }
-        const float scale = kFourPi / (float)a.S;
+                // a list that overflowed and is still transparent: traverse on
+                if (done || k_over == kNoHit) pending = false;
+                // Add this round to the source's transfer (the D lanes of a
+                // source summed first), so that the sums are dead during the
+                // next traversal.
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch)
+                for (int ch = 0; ch < 3; ++ch) {
+                    float* out = a.transfer + ((size_t)orig * 3 + ch) * K;
 #pragma unroll
-            for (int k = 0; k < K; ++k) acc[ch][k] = segment_sum(acc[ch][k], D) * scale;
-        if (valid && (lane % D) == 0) {
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float* out = a.transfer + ((size_t)orig * 3 + ch) * K;
-#pragma unroll
-                for (int k = 0; k < K; ++k) out[k] += acc[ch][k];
+                    for (int k = 0; k < K; ++k) {
+                        const float v = segment_sum(acc[ch][k], D) * scale;
+                        if (valid && (lane % D) == 0) out[k] += v;
+                        acc[ch][k] = 0.0f;
+                    }
+                }
             }
         }
     }
