@@ -299,6 +299,7 @@ __device__ inline int key_j(uint64_t k) { return (int)(uint32_t)k; }
 // so the lists are sized by the waves, not the scene.
 constexpr int kBlend = 8;   // hits selected per pass over the list
 constexpr int kScan = 8;    // list entries loaded together
+constexpr int kCheck = 8;   // depth checkpoints per ray and round
 
 template <int K>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void bounce_kernel(TransferArgs a)
@@ -366,6 +367,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 uint64_t k_over = kNoHit;   // hits from here on wait for the next round
                 bool live = pending;
                 float tlo = started ? fmaxf(hp.t_min, key_t(k_last)) : hp.t_min, thi = tc;
+                // Checkpoints tlo + (b + 1) tstep split [tlo, tc]: P[b] is T times
+                // the (1 - alpha) of the hits found so far in front of checkpoint
+                // b.  The hits in front of it are a subset of all of them, so
+                // once P[b] < T_eps the walk ends there and nothing beyond the
+                // checkpoint is needed.
+                const float tstep = tc < INFINITY ? (tc - tlo) * (1.0f / (float)kCheck) : 0.0f;
+                float P[kCheck];
+#pragma unroll
+                for (int b = 0; b < kCheck; ++b) P[b] = T;
                 // Full list: keep the hits in front of their mean depth (at least
                 // one goes: if rounding keeps them all, the farthest).
                 auto compact = [&]() {
@@ -408,8 +418,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                     HitResult h;
                     const bool hit = gaussian_exact(p, q, ox, oy, oz, d, hp, h) & cand;
                     const uint64_t key = hit_key(h.t, r);
-                    const bool ins = hit & (h.t <= tc) & (!started | (key > k_last)) & (key < k_over);
+                    const bool ins = hit & (h.t <= thi) & (!started | (key > k_last)) & (key < k_over);
                     if (ins) {
+                        if (tstep > 0.0f) {
+                            float cut = thi;
+#pragma unroll
+                            for (int b = 0; b < kCheck; ++b) {
+                                const float tb = tlo + tstep * (float)(b + 1);
+                                P[b] = h.t <= tb ? P[b] * (1.0f - h.alpha) : P[b];
+                                cut = P[b] < hp.T_eps ? fminf(cut, tb) : cut;
+                            }
+                            thi = cut;
+                        }
                         if (cnt == M) compact();
                         if (key < k_over) {
                             lkey[cnt * kWave] = key;
