@@ -160,6 +160,20 @@ def hit_set(scene, num_dirs, seed=0, cut=None, sources=None, margins=DEFAULT_MAR
     return np.nonzero(mark)[0].astype(np.int64)
 
 
+def rays_vis(scene, sources, dirs, cut=None, threads=None):
+    """Visibility V[r] of the ray from the centre of Gaussian sources[r]
+    along dirs[r] (unit), through every other Gaussian."""
+    means, quats, log_scales, opacity, _ = _scene_arrays(scene)
+    n = means.shape[0]
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    w = _f64(dirs).reshape(-1, 3)
+    V = np.empty(src.shape[0])
+    _lib().ora_rays_vis(ctypes.c_int(n), _p(means), _p(quats), _p(log_scales), _p(opacity),
+                        ctypes.c_int(src.shape[0]), _p(src), _p(w), _p(_cut_array(cut)), _p(V),
+                        ctypes.c_int(threads or default_threads()))
+    return V
+
+
 def bounce_transfer(scene, num_dirs, bands, t_dir_rows, t_dir_index, allow_dir_rows=None, seed=0,
                     cut=None, sources=None, want_allow=False, margins=DEFAULT_MARGINS, threads=None):
     """One-bounce indirect transfer t_ind[count, 3, K] of the listed sources.

@@ -360,6 +360,22 @@ int ora_direct(int n, const double* means, const double* quats, const double* lo
     return 0;
 }
 
+/* Visibility of single rays: V[r] for the ray from the centre of Gaussian
+ * sources[r] along the unit direction w[r] (Eq. 4's product over every other
+ * Gaussian, 0 below T_eps), for the per-ray gradient references. */
+int ora_rays_vis(int n, const double* means, const double* quats, const double* log_scales,
+                 const double* opacity, int count, const int* sources, const double* w, const double* cut,
+                 double* V, int threads)
+{
+    OraGauss* g = ora_setup(n, means, quats, log_scales, opacity);
+    int nt = ora_threads(threads);
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
+    for (int r = 0; r < count; ++r)
+        V[r] = ora_ray_vis(g, n, sources[r], w + 3 * (size_t)r, cut, NULL, NULL, NULL);
+    free(g);
+    return 0;
+}
+
 /* Indices of every Gaussian that some traced ray of the listed sources hits
  * (mark[j] = 1), ambiguous hits included. */
 int ora_hit_set(int n, const double* means, const double* quats, const double* log_scales,

@@ -1,0 +1,181 @@
+"""Full-size workloads, in the launch configuration the benchmark times.
+
+The oracle is brute force, so at these sizes it checks sampled outputs one by
+one (the transfer of randomly drawn sources); where no sampled output is
+within its reach (the bounce needs the direct transfer of every splat a ray
+hits, the gradient needs the whole forward), properties that hold at any size
+are checked instead.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import scenegen
+from helpers import as_f32, assert_transfer_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def prt():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2408_03538_amd as p
+    return p
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _workload_scene(name):
+    w = scenegen.workload(name)
+    return w, as_f32(w["scene"])
+
+
+def test_surface100k_sampled_sources(prt, oracle_mod):
+    """100,000-splat surface scene, S = 256, 16 coeffs: 48 sources against
+    the oracle."""
+    w, scene = _workload_scene("surface100k")
+    _say("surface100k: build + transfer")
+    sc = prt.Scene.from_arrays(scene)
+    bvh = prt.build_bvh(sc, check=True)
+    params = prt.TransferParams(num_dirs=w["num_dirs"], sh_bands=w["bands"])
+    t = prt.precompute_transfer(sc, bvh, params, check=True).cpu().numpy()
+    assert np.isfinite(t).all()
+    src = np.random.default_rng(100).choice(scene["means"].shape[0], 48, replace=False)
+    _say("surface100k: oracle on 48 sources")
+    ref = oracle_mod.direct_transfer(scene, w["num_dirs"], w["bands"], sources=src, want_allow=True)
+    err = assert_transfer_parity(t[src, 0, :], ref["t"], ref["allow"])
+    _say(f"surface100k: max |dt| = {err:.2e}")
+
+
+def test_million_direct_sampled_sources(prt, oracle_mod):
+    """1,000,000 splats (surface + 20 shells), S = 512, 16 coeffs: the direct
+    transfer of 6 sources against the oracle."""
+    w, scene = _workload_scene("million")
+    _say("million: build + direct transfer")
+    sc = prt.Scene.from_arrays(scene)
+    bvh = prt.build_bvh(sc, check=True)
+    params = prt.TransferParams(num_dirs=w["num_dirs"], sh_bands=w["bands"])
+    t = prt.precompute_transfer(sc, bvh, params, check=True)[:, 0, :].cpu().numpy()
+    assert np.isfinite(t).all()
+    n = scene["means"].shape[0]
+    rng = np.random.default_rng(101)
+    # three surface splats, three shell splats
+    src = np.concatenate([rng.choice(200_000, 3, replace=False), 200_000 + rng.choice(n - 200_000, 3, replace=False)])
+    _say("million: oracle on 6 sources")
+    ref = oracle_mod.direct_transfer(scene, w["num_dirs"], w["bands"], sources=src, want_allow=True)
+    err = assert_transfer_parity(t[src], ref["t"], ref["allow"])
+    _say(f"million: max |dt| = {err:.2e}")
+
+
+def test_million_bounce_properties(prt):
+    """The one-bounce pass on the full million-splat scene.  With albedo
+    (a, 2a, 0) the blue channel must be the direct transfer bit for bit, the
+    green bounce term twice the red one (scaling by 2 is exact), the bounce
+    DC term non-negative and, per ray, the blend weights at most the occluded
+    fraction 1 - V, so that
+      t_ind[i, c, 0] <= (4 pi / S) sum_s c_s (1 - V_s) max_j rho_jc t_dir[j, 0] / pi."""
+    import torch
+    w, scene = _workload_scene("million")
+    n = scene["means"].shape[0]
+    a = scene["albedo"][:, 0].copy()
+    scene["albedo"] = np.stack([a, 2.0 * a, np.zeros_like(a)], axis=1)
+    sc = prt.Scene.from_arrays(scene)
+    bvh = prt.build_bvh(sc, check=True)
+    S, bands = w["num_dirs"], w["bands"]
+    _say("million: direct transfer with visibility")
+    td, vis = prt.precompute_transfer(sc, bvh, prt.TransferParams(num_dirs=S, sh_bands=bands), want_vis=True,
+                                      check=True)
+    _say("million: direct + bounce")
+    tb = prt.precompute_transfer(sc, bvh, prt.TransferParams(num_dirs=S, sh_bands=bands, bounces=1), check=True)
+    assert torch.equal(tb[:, 2], td[:, 0])
+    d = td[:, 0].double()
+    ind0 = tb[:, 0].double() - d
+    ind1 = tb[:, 1].double() - d
+    scale = d.abs() + 1.0
+    lin = ((ind1 - 2.0 * ind0).abs() / scale).max().item()
+    assert lin < 2e-5, lin
+    assert ind0[:, 0].min().item() > -2e-5
+    assert ind0.abs().max().item() > 1e-2          # the bounce is not negligible
+    # the bound on the DC term, for 2,000 sampled sources
+    rows = np.random.default_rng(102).choice(n, 2000, replace=False)
+    rows_t = torch.tensor(rows, device=td.device)
+    V = vis[rows_t].double().cpu().numpy()
+    dirs = prt.direction_table(S, 0, bands)[2].double().cpu().numpy()
+    c = scene["normals"][rows] @ dirs.T
+    occluded = np.where(c > 0, c * (1.0 - np.clip(V, 0.0, 1.0)), 0.0).sum(1)
+    rho_t = (torch.tensor(scene["albedo"][:, 0], device=td.device, dtype=torch.float64) * td[:, 0, 0].double())
+    bound = (4 * math.pi / S) * occluded * rho_t.max().item() / math.pi
+    got = ind0[rows_t, 0].cpu().numpy()
+    assert (got <= bound + 2e-5).all(), float((got - bound).max())
+    _say(f"million bounce: linearity {lin:.1e}, max bounce DC {got.max():.3f} (bound {bound.max():.3f})")
+
+
+def test_relight3m_full(prt, oracle_mod):
+    """3,000,000 RGB transfers x 64 lights in FP32, BF16 and F16 storage:
+    sampled colours against the FP64 product, relative to sum |T| |L|."""
+    import torch
+    w = scenegen.workload("relight3m")
+    T64 = np.asarray(w["transfer"], np.float32).astype(np.float64)
+    L64 = np.asarray(w["light"], np.float32).astype(np.float64)
+    T = torch.tensor(T64, dtype=torch.float32, device="cuda")
+    L = torch.tensor(L64, dtype=torch.float32, device="cuda")
+    rows = np.random.default_rng(103).choice(T.shape[0], 20000, replace=False)
+    ref = oracle_mod.relight(T64[rows], L64)
+    scale = np.einsum("nck,bck->nbc", np.abs(T64[rows]), np.abs(L64))
+    rows_t = torch.tensor(rows, device="cuda")
+    bounds = {("f32", "f32"): 2e-6, ("bf16", "f16"): 1e-2, ("f16", "f16"): 1e-2, ("bf16", "f32"): 1e-2}
+    for (tdt, odt), bound in bounds.items():
+        _say(f"relight3m: {tdt} -> {odt}")
+        t = T if tdt == "f32" else prt.pack(T, tdt)
+        out = prt.relight(t, L, out_dtype=odt)
+        got = out[rows_t].double().cpu().numpy()
+        rel = np.abs(got - ref) / scale
+        assert rel.max() <= bound, (tdt, odt, rel.max())
+        _say(f"relight3m {tdt} -> {odt}: max rel err {rel.max():.2e}, mean {rel.mean():.2e}")
+        del out
+
+
+def test_grad200k_sampled_gaussians(prt):
+    """200,000 surface splats, S = 256, 16 coeffs, transfer + relight under a
+    linear loss sum(W * colour) with fixed random W: the adjoint's gradient
+    with respect to the opacity, log-scales, quaternion and normal of 8
+    sampled Gaussians against the FP64 oracle (per-ray references: these
+    parameters act only through alpha_j on the rays that hit j, and through
+    j's own rays for the normal).  Central differences are no check at this
+    size: grazing rays along the surfaces put many peak depths within FP32
+    rounding of t_min, and a step of 1e-4 already flips some of them."""
+    import torch
+    from oracle.grad import gaussian_param_grads
+    w, scene = _workload_scene("grad200k")
+    n = scene["means"].shape[0]
+    keys = ("means", "quats", "log_scales", "opacity", "normals")
+    params = prt.TransferParams(num_dirs=w["num_dirs"], sh_bands=w["bands"])
+    L64 = np.asarray(w["light"], np.float32).astype(np.float64)
+    W64 = np.random.default_rng(104).standard_normal((n, 1, 3)).astype(np.float32).astype(np.float64)
+    light = torch.tensor(L64, dtype=torch.float32, device="cuda")
+    Wt = torch.tensor(W64, dtype=torch.float32, device="cuda")
+    ten = {k: torch.tensor(scene[k], dtype=torch.float32, device="cuda", requires_grad=True) for k in keys}
+    _say("grad200k: forward + backward")
+    col = prt.transfer_and_relight(*[ten[k] for k in keys], light, params)
+    (col * Wt).sum().backward()
+    g = {k: ten[k].grad.double().cpu().numpy() for k in keys}
+    dT = np.einsum("nbc,bck->nk", W64, L64)              # d loss / d transfer
+    picks = np.random.default_rng(105).choice(n, 8, replace=False)
+    refs = []
+    for j in picks:
+        _say(f"grad200k: oracle for Gaussian {j}")
+        refs.append(gaussian_param_grads(scene, int(j), w["num_dirs"], w["bands"], dT))
+    for key in ("opacity", "log_scales", "quats", "normals"):
+        scale = max(np.abs(np.asarray(r["grads"][key])).max() for r in refs)
+        for j, r in zip(picks, refs):
+            ref = np.asarray(r["grads"][key], dtype=np.float64)
+            got = np.asarray(g[key][j], dtype=np.float64)
+            tol = 1e-3 * np.maximum(np.abs(ref), 1e-2 * scale) + np.asarray(r["allow"][key])
+            assert (np.abs(got - ref) <= tol).all(), (key, int(j), got, ref, r["allow"][key])
+        _say(f"grad200k {key}: ok (largest |g| {scale:.3e})")
