@@ -202,17 +202,20 @@ prtgs_status prtgs_relight_backward(int32_t n, int32_t K, int32_t C, const float
 /* ---------------------------------------------------------------------- */
 /* Adjoint of the direct transfer (bounces == 0): given d_transfer [n][1][K]*/
 /* = dLoss/dt_dir, accumulates dLoss/d(means, quats, log_scales, opacity,   */
-/* normals) into `grads`.  Every ray is traced again (hit lists are not     */
-/* stored); the gradient is that of the piecewise-smooth forward with the   */
-/* hit, hemisphere and opacity-cutoff decisions held fixed.  Atomic         */
-/* accumulation: summation order, hence the last bits, may vary between     */
-/* runs.  ws: prtgs_transfer_backward_workspace_bytes.                      */
+/* normals) into `grads`.  Hit lists are not stored: every ray is traced    */
+/* again for its per-hit terms.  vis (may be NULL): the [n][S] visibilities */
+/* that prtgs_precompute_transfer returned for the same Gaussians, BVH and  */
+/* parameters over all sources; with it each ray is traced once, without it */
+/* twice (visibility first).  The gradient is that of the piecewise-smooth  */
+/* forward with the hit, hemisphere and opacity-cutoff decisions held       */
+/* fixed.  Atomic accumulation: summation order, hence the last bits, may   */
+/* vary between runs.  ws: prtgs_transfer_backward_workspace_bytes.         */
 /* ---------------------------------------------------------------------- */
 size_t prtgs_transfer_backward_workspace_bytes(const prtgs_transfer_desc* d /* host */, int32_t n);
 prtgs_status prtgs_transfer_backward(const prtgs_gaussians* g /* host */, const void* bvh,
                                      const prtgs_transfer_desc* d /* host */, const float* d_transfer,
-                                     const prtgs_grads* grads /* host struct */, void* ws,
-                                     size_t ws_bytes, hipStream_t stream);
+                                     const float* vis, const prtgs_grads* grads /* host struct */,
+                                     void* ws, size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -62,7 +62,7 @@ SIGNATURES = {
                                          c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "prtgs_transfer_backward_workspace_bytes": (c_size_t, [ctypes.POINTER(TransferDesc), c_int32]),
     "prtgs_transfer_backward": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, ctypes.POINTER(TransferDesc),
-                                          c_void_p, ctypes.POINTER(Grads), c_void_p, c_size_t, c_void_p]),
+                                          c_void_p, c_void_p, ctypes.POINTER(Grads), c_void_p, c_size_t, c_void_p]),
 }
 
 _handle = None

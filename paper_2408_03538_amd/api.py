@@ -277,9 +277,12 @@ def relight_backward(transfer: torch.Tensor, light: torch.Tensor, d_colour: torc
 
 
 def transfer_backward(scene: Scene, bvh: Bvh, params: TransferParams, d_transfer: torch.Tensor,
-                      grads: dict | None = None, workspace: Workspace | None = None, check: bool = False) -> dict:
+                      grads: dict | None = None, workspace: Workspace | None = None, check: bool = False,
+                      vis: torch.Tensor | None = None) -> dict:
     """dLoss/d(means, quats, log_scales, opacity, normals) from dLoss/dtransfer
-    (direct transfer, [n, 1, K]); accumulated into ``grads`` if given."""
+    (direct transfer, [n, 1, K]); accumulated into ``grads`` if given.
+    ``vis``: the forward's per-ray visibilities [n, S] (all sources), which
+    spare the backward one traversal per ray."""
     lib = _lib.load()
     n = scene.n
     dev = scene.device
@@ -297,7 +300,9 @@ def transfer_backward(scene: Scene, bvh: Bvh, params: TransferParams, d_transfer
         raise _lib.PrtgsError(1, "invalid transfer parameters")
     ws = (workspace or Workspace()).get(wbytes, dev)
     dt = d_transfer.to(F32).contiguous()
-    _lib.check(lib.prtgs_transfer_backward(ctypes.byref(g), _ptr(bvh.buffer), ctypes.byref(d), _ptr(dt),
+    if vis is not None and (vis.shape != (n, params.num_dirs) or vis.dtype != F32 or not vis.is_contiguous()):
+        raise ValueError("vis must be a contiguous float32 [n, num_dirs] tensor")
+    _lib.check(lib.prtgs_transfer_backward(ctypes.byref(g), _ptr(bvh.buffer), ctypes.byref(d), _ptr(dt), _ptr(vis),
                                            ctypes.byref(gr), _ptr(ws), ws.numel(), _stream()))
     if check:
         check_flags(ws, "transfer_backward")

@@ -24,10 +24,11 @@ class PRTGSTransfer(torch.autograd.Function):
                           log_scales.detach().contiguous(), opacity.detach().contiguous(),
                           normals.detach().contiguous())
         bvh = api.build_bvh(scene)
-        transfer = api.precompute_transfer(scene, bvh, params)
+        # the per-ray visibilities spare the adjoint one traversal per ray
+        transfer, vis = api.precompute_transfer(scene, bvh, params, want_vis=True)
         colour = api.relight(transfer, light.detach())
         ctx.save_for_backward(light)
-        ctx.scene, ctx.bvh, ctx.params, ctx.transfer = scene, bvh, params, transfer
+        ctx.scene, ctx.bvh, ctx.params, ctx.transfer, ctx.vis = scene, bvh, params, transfer, vis
         return colour
 
     @staticmethod
@@ -35,7 +36,7 @@ class PRTGSTransfer(torch.autograd.Function):
         (light,) = ctx.saved_tensors
         dT, dL = api.relight_backward(ctx.transfer, light.detach(), d_colour,
                                       want_dT=True, want_dL=ctx.needs_input_grad[5])
-        grads = api.transfer_backward(ctx.scene, ctx.bvh, ctx.params, dT)
+        grads = api.transfer_backward(ctx.scene, ctx.bvh, ctx.params, dT, vis=ctx.vis)
         return (grads["means"], grads["quats"], grads["log_scales"], grads["opacity"], grads["normals"],
                 dL.to(light.dtype) if dL is not None else None, None)
 

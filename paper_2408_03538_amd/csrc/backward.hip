@@ -106,23 +106,28 @@ __global__ __launch_bounds__(kBlock) void transfer_backward_kernel(BackwardArgs 
         for (int k = 0; k < K; ++k) g = fmaf(dt[k], a.Y[(size_t)s * K + k], g);
         g *= wq;
         const BatchDir bd = batch_dir(d, traced);
-        // pass 1: transmittance
         bool live = traced;
         float T = 1.0f;
         float tlo = hp.t_min, thi = INFINITY;
-        auto leaf1 = [&](int r, bool box_hit) {
-            const Prim p = uniform_load(a.prims, r);
-            const PreHit q = gaussian_pre(p, ox, oy, oz, d, hp);
-            const bool cand = q.maybe & box_hit & live & (r != rank);
-            if (__ballot(cand) == 0ull) return;
-            HitResult h;
-            const bool hit = gaussian_exact(p, q, ox, oy, oz, d, hp, h) & cand;
-            T = hit ? T * (1.0f - h.alpha) : T;
-            const bool opaque = T < hp.T_eps;
-            live = live & !opaque;
-            T = opaque ? 0.0f : T;
-        };
-        traverse_batch(a, d, bd, ox, oy, oz, live, tlo, thi, leaf1);
+        if (ba.vis_in) {
+            // the forward's visibility of this ray (negative: not traced there)
+            T = traced ? fmaxf(ba.vis_in[(size_t)orig * a.S + s], 0.0f) : 0.0f;
+        } else {
+            // pass 1: transmittance
+            auto leaf1 = [&](int r, bool box_hit) {
+                const Prim p = uniform_load(a.prims, r);
+                const PreHit q = gaussian_pre(p, ox, oy, oz, d, hp);
+                const bool cand = q.maybe & box_hit & live & (r != rank);
+                if (__ballot(cand) == 0ull) return;
+                HitResult h;
+                const bool hit = gaussian_exact(p, q, ox, oy, oz, d, hp, h) & cand;
+                T = hit ? T * (1.0f - h.alpha) : T;
+                const bool opaque = T < hp.T_eps;
+                live = live & !opaque;
+                T = opaque ? 0.0f : T;
+            };
+            traverse_batch(a, d, bd, ox, oy, oz, live, tlo, thi, leaf1);
+        }
         const bool carries = traced && T > 0.0f;
         if (carries) {
             gni[0] += g * T * d.wx;

@@ -376,8 +376,8 @@ size_t prtgs_transfer_backward_workspace_bytes(const prtgs_transfer_desc* d, int
 }
 
 prtgs_status prtgs_transfer_backward(const prtgs_gaussians* g, const void* bvh, const prtgs_transfer_desc* d,
-                                     const float* d_transfer, const prtgs_grads* grads, void* ws, size_t ws_bytes,
-                                     hipStream_t stream)
+                                     const float* d_transfer, const float* vis, const prtgs_grads* grads, void* ws,
+                                     size_t ws_bytes, hipStream_t stream)
 {
     prtgs_status st = check_desc(d);
     if (st != PRTGS_OK) return st;
@@ -430,6 +430,7 @@ prtgs_status prtgs_transfer_backward(const prtgs_gaussians* g, const void* bvh, 
     a.fwd.G = group_size(n);
     a.fwd.flags = flags;
     a.d_transfer = d_transfer;
+    a.vis_in = vis;
     a.g_W = scratch;
     a.g_mu = scratch + 9 * (size_t)n;
     a.g_o = scratch + 12 * (size_t)n;

@@ -160,6 +160,7 @@ inline int bounce_waves(int n) { return n < kBounceWaves ? n : kBounceWaves; }
 struct BackwardArgs {
     TransferArgs fwd;
     const float* d_transfer;  // [n][1][K]
+    const float* vis_in;      // [n][S] forward visibilities (original order), or null
     float* g_W;               // [n][9] scratch: dLoss/dW, leaf order
     float* g_mu;              // [n][3] scratch, leaf order
     float* g_o;               // [n]    scratch, leaf order

@@ -96,7 +96,8 @@ def test_backward_rejects_bounce(lib):
     g = _lib.Gaussians(10, 256, 256, 256, 256, 256, 256)
     d = _lib.TransferDesc(64, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99)
     gr = _lib.Grads(None, None, None, None, None)
-    st = lib.prtgs_transfer_backward(ctypes.byref(g), 256, ctypes.byref(d), 256, ctypes.byref(gr), 256, 1 << 30, None)
+    st = lib.prtgs_transfer_backward(ctypes.byref(g), 256, ctypes.byref(d), 256, None, ctypes.byref(gr), 256, 1 << 30,
+                                     None)
     assert st == 3
 
 
