@@ -86,14 +86,20 @@ __global__ __launch_bounds__(kThreadsF32) void relight_f32_kernel(int n, const f
 // ~FP32 precision; columns of other channels get zeros (C == 3 needs C such
 // steps).  Lane l holds A[l % 16][8 (l / 16) + 0..7], B[8 (l / 16) + 0..7][l % 16]
 // and D[4 (l / 16) + 0..3][l % 16].
-// Work item = (16-row tile, chunk of CT column tiles).  Every wave works on
-// its own items (no block barrier): it keeps the B fragments of one column
-// chunk in registers and walks row tiles; each result tile goes through a
-// wave-private LDS patch so that the 16 rows x 16 CT columns leave in 16-byte
-// stores (each row of the chunk is contiguous in memory).
+// Work item = one 16-row tile against a group of up to kGroupTiles column
+// tiles (192 output columns: every light of a 64-light batch), so each
+// transfer row is read once per group.  The block builds the B fragments of
+// its group once, in LDS; each wave then walks row tiles on its own (no
+// block barrier after the set-up), loading its A fragments once per tile and
+// producing the group's columns in chunks of CT tiles.  Each chunk's result
+// goes through a wave-private LDS patch so that its 16 rows x 16 CT columns
+// leave in 16-byte stores (each row of a chunk is contiguous in memory).
 
-constexpr int kWavesMfma = 4;
+// waves per block: 4 with 16-bit colours, 8 with FP32 colours (measured)
+template <bool OUT16>
+constexpr int waves_mfma() { return OUT16 ? 4 : 8; }
 constexpr int kChunkTiles = 4;   // column tiles per chunk (64 output columns)
+constexpr int kGroupTiles = 12;  // column tiles per group (3 chunks)
 
 template <bool BF>
 struct Frag;
@@ -113,33 +119,31 @@ struct Frag<false> {
 };
 
 template <int K, int C, bool BF, bool OUT16>
-__global__ __launch_bounds__(kWavesMfma * kWave) void relight_mfma_kernel(int n, const void* __restrict__ Tv, int B,
+__global__ __launch_bounds__(waves_mfma<OUT16>() * kWave) void relight_mfma_kernel(int n, const void* __restrict__ Tv, int B,
                                                                           const float* __restrict__ L,
-                                                                          void* __restrict__ out, int waves_per_chunk)
+                                                                          void* __restrict__ out)
 {
     using F = Frag<BF>;
     using vec = typename F::vec;
     using elem = typename F::elem;
     constexpr int CT = kChunkTiles;
+    constexpr int kWavesMfma = waves_mfma<OUT16>();
     constexpr int kOutBytes = OUT16 ? 2 : 4;
     constexpr int kRowBytes = CT * 16 * kOutBytes;          // one row of a chunk: 128 or 256 B
+    __shared__ vec bsh[kGroupTiles][C][kWave];
     __shared__ __align__(16) unsigned char stage[kWavesMfma][16 * kRowBytes];
     const elem* T = static_cast<const elem*>(Tv);
     const int lane = threadIdx.x & (kWave - 1);
     const int wslot = threadIdx.x / kWave;
-    const int gwave = blockIdx.x * kWavesMfma + wslot;
-    const int cols = 3 * B;
-    const int nchunks = (cols + 16 * CT - 1) / (16 * CT);
-    const int chunk = gwave % nchunks;
-    const int wave_in_chunk = gwave / nchunks;
-    if (wave_in_chunk >= waves_per_chunk) return;
     const int g = lane / 16;   // k group of the lane's A/B fragment
     const int li = lane % 16;  // row (A) / column (B, D) of the lane
+    const int cols = 3 * B;
+    const int group_col0 = blockIdx.y * kGroupTiles * 16;
+    const int group_tiles = min(kGroupTiles, (cols - group_col0 + 15) / 16);
 
-    vec bfrag[CT][C];
-#pragma unroll
-    for (int m = 0; m < CT; ++m) {
-        const int col = (chunk * CT + m) * 16 + li;
+    // B fragments of the group's column tiles (wave w builds tiles w, w + 4, ...)
+    for (int m = wslot; m < group_tiles; m += kWavesMfma) {
+        const int col = group_col0 + m * 16 + li;
         const bool cvalid = col < cols;
         const int ch = cvalid ? col % 3 : 0;
 #pragma unroll
@@ -157,15 +161,15 @@ __global__ __launch_bounds__(kWavesMfma * kWave) void relight_mfma_kernel(int n,
                 }
                 v[e] = F::from_float(x);
             }
-            bfrag[m][st] = v;
+            bsh[m][st][lane] = v;
         }
     }
+    __syncthreads();
 
     unsigned char* my_stage = stage[wslot];
     const int ntiles_rows = (n + 15) / 16;
-    const int chunk_col0 = chunk * CT * 16;
-    const int chunk_cols = min(CT * 16, cols - chunk_col0);
-    for (int rt = wave_in_chunk; rt < ntiles_rows; rt += waves_per_chunk) {
+    const size_t row_stride = (size_t)cols * kOutBytes;
+    for (int rt = blockIdx.x * kWavesMfma + wslot; rt < ntiles_rows; rt += gridDim.x * kWavesMfma) {
         const int64_t row = (int64_t)rt * 16 + li;
         const bool rvalid = row < n;
         vec afrag[C];
@@ -183,52 +187,57 @@ __global__ __launch_bounds__(kWavesMfma * kWave) void relight_mfma_kernel(int n,
                 afrag[st] = v;
             }
         }
-#pragma unroll
-        for (int m = 0; m < CT; ++m) {
-            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int st = 0; st < C; ++st) acc = F::mma(afrag[st], bfrag[m][st], acc);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = 4 * g + v;
-                const int c = m * 16 + li;
-                if (OUT16) reinterpret_cast<__half*>(my_stage)[r * CT * 16 + c] = __float2half(acc[v]);
-                else reinterpret_cast<float*>(my_stage)[r * CT * 16 + c] = acc[v];
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // 16 rows x kRowBytes, in 16-byte pieces; every row of the chunk is contiguous
-        constexpr int kPiecesPerRow = kRowBytes / 16;
         const int nrows = (int)min((int64_t)16, (int64_t)n - (int64_t)rt * 16);
-        const size_t row_stride = (size_t)cols * kOutBytes;
-        unsigned char* obase = static_cast<unsigned char*>(out) + (size_t)rt * 16 * row_stride +
-                               (size_t)chunk_col0 * kOutBytes;
-        const bool full_chunk = chunk_cols == CT * 16 && (row_stride % 16) == 0 &&
-                                (reinterpret_cast<uintptr_t>(out) % 16) == 0;
-        if (full_chunk) {
+        for (int m0 = 0; m0 < group_tiles; m0 += CT) {
+            const int chunk_col0 = group_col0 + m0 * 16;
+            const int chunk_cols = min(CT * 16, cols - chunk_col0);
 #pragma unroll
-            for (int pc = lane; pc < 16 * kPiecesPerRow; pc += kWave) {
-                const int r = pc / kPiecesPerRow, piece = pc % kPiecesPerRow;
-                if (r < nrows)
-                    *reinterpret_cast<uint4*>(obase + r * row_stride + piece * 16) =
-                        *reinterpret_cast<const uint4*>(my_stage + r * kRowBytes + piece * 16);
-            }
-        } else {
-            for (int e = lane; e < 16 * chunk_cols; e += kWave) {
-                const int r = e / chunk_cols, c = e % chunk_cols;
-                if (r < nrows) {
-                    if (OUT16)
-                        reinterpret_cast<__half*>(obase + r * row_stride)[c] =
-                            reinterpret_cast<const __half*>(my_stage)[r * CT * 16 + c];
-                    else
-                        reinterpret_cast<float*>(obase + r * row_stride)[c] =
-                            reinterpret_cast<const float*>(my_stage)[r * CT * 16 + c];
+            for (int m = 0; m < CT; ++m) {
+                if (m0 + m < group_tiles) {
+                    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int st = 0; st < C; ++st) acc = F::mma(afrag[st], bsh[m0 + m][st][lane], acc);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 4 * g + v;
+                        const int c = m * 16 + li;
+                        if (OUT16) reinterpret_cast<__half*>(my_stage)[r * CT * 16 + c] = __float2half(acc[v]);
+                        else reinterpret_cast<float*>(my_stage)[r * CT * 16 + c] = acc[v];
+                    }
                 }
             }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            // 16 rows x kRowBytes, in 16-byte pieces; every row of the chunk is contiguous
+            constexpr int kPiecesPerRow = kRowBytes / 16;
+            unsigned char* obase = static_cast<unsigned char*>(out) + (size_t)rt * 16 * row_stride +
+                                   (size_t)chunk_col0 * kOutBytes;
+            const bool full_chunk = chunk_cols == CT * 16 && (row_stride % 16) == 0 &&
+                                    (reinterpret_cast<uintptr_t>(out) % 16) == 0;
+            if (full_chunk) {
+#pragma unroll
+                for (int pc = lane; pc < 16 * kPiecesPerRow; pc += kWave) {
+                    const int r = pc / kPiecesPerRow, piece = pc % kPiecesPerRow;
+                    if (r < nrows)
+                        *reinterpret_cast<uint4*>(obase + r * row_stride + piece * 16) =
+                            *reinterpret_cast<const uint4*>(my_stage + r * kRowBytes + piece * 16);
+                }
+            } else {
+                for (int e = lane; e < 16 * chunk_cols; e += kWave) {
+                    const int r = e / chunk_cols, c = e % chunk_cols;
+                    if (r < nrows) {
+                        if (OUT16)
+                            reinterpret_cast<__half*>(obase + r * row_stride)[c] =
+                                reinterpret_cast<const __half*>(my_stage)[r * CT * 16 + c];
+                        else
+                            reinterpret_cast<float*>(obase + r * row_stride)[c] =
+                                reinterpret_cast<const float*>(my_stage)[r * CT * 16 + c];
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
 }
 
@@ -319,25 +328,28 @@ hipError_t f32_dispatch(int n, const float* T, int B, const float* L, void* out,
     return f32_dispatch_out<K, C, 3>(n, T, B, L, out, out16, stream);
 }
 
+template <int K, int C, bool BF, bool OUT16>
+hipError_t mfma_launch(int n, const void* T, int B, const float* L, void* out, hipStream_t stream)
+{
+    constexpr int kWavesMfma = waves_mfma<OUT16>();
+    const int cols = 3 * B;
+    const int groups = (cols + 16 * kGroupTiles - 1) / (16 * kGroupTiles);
+    const int row_tiles = (n + 15) / 16;
+    // about 8 waves per SIMD over 256 CUs in all, walking the row tiles
+    int blocks = (256 * 4 * 8 / kWavesMfma + groups - 1) / groups;
+    const int need = (row_tiles + kWavesMfma - 1) / kWavesMfma;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((relight_mfma_kernel<K, C, BF, OUT16>), dim3(blocks, groups), dim3(kWavesMfma * kWave), 0,
+                       stream, n, T, B, L, out);
+    return hipGetLastError();
+}
+
 template <int K, int C, bool BF>
 hipError_t mfma_dispatch(int n, const void* T, int B, const float* L, void* out, bool out16, hipStream_t stream)
 {
-    const int cols = 3 * B;
-    const int nchunks = (cols + 16 * kChunkTiles - 1) / (16 * kChunkTiles);
-    const int row_tiles = (n + 15) / 16;
-    // about 8 waves per SIMD over 256 CUs, split evenly over the column chunks
-    int waves_per_chunk = (256 * 4 * 8 + nchunks - 1) / nchunks;
-    if (waves_per_chunk > row_tiles) waves_per_chunk = row_tiles;
-    if (waves_per_chunk < 1) waves_per_chunk = 1;
-    const int waves = waves_per_chunk * nchunks;
-    const int blocks = (waves + kWavesMfma - 1) / kWavesMfma;
-    if (out16)
-        hipLaunchKernelGGL((relight_mfma_kernel<K, C, BF, true>), dim3(blocks), dim3(kWavesMfma * kWave), 0, stream, n,
-                           T, B, L, out, waves_per_chunk);
-    else
-        hipLaunchKernelGGL((relight_mfma_kernel<K, C, BF, false>), dim3(blocks), dim3(kWavesMfma * kWave), 0, stream, n,
-                           T, B, L, out, waves_per_chunk);
-    return hipGetLastError();
+    if (out16) return mfma_launch<K, C, BF, true>(n, T, B, L, out, stream);
+    return mfma_launch<K, C, BF, false>(n, T, B, L, out, stream);
 }
 
 template <int K, int C>
