@@ -13,6 +13,7 @@ are torch float64 autograd through a separate re-expression of the forward
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -225,6 +226,73 @@ def full_transfer(scene, num_dirs, bands, bounces, seed=0, cut=None, sources=Non
     if want_allow:
         allow = d["allow"][:, None, :] + b["allow"]
     return dict(t=t, allow=allow, t_dir=d["t"], t_ind=b["t"])
+
+
+# ----------------------------------------------------------------------------
+# the paper's own bounce: index matrix + recursive self-transfer
+# (Sec. 4.4 Eq. 26 and the filter after Eq. 27; Sec. 4.5 Eq. 32-35)
+# ----------------------------------------------------------------------------
+
+def index_matrix(scene, num_dirs, seed=0, cut=None, t_same=1.0, sources=None, margins=DEFAULT_MARGINS,
+                 threads=None):
+    """idx[count, S]: per ray the hit of largest W = alpha T max(-w.n_j, 0)
+    among hits with T <= t_same (-1: none, or not traced); amb[count, S]:
+    rays whose choice lies within FP32 rounding of a tie or threshold."""
+    means, quats, log_scales, opacity, normals = _scene_arrays(scene)
+    n = means.shape[0]
+    dirs = directions(num_dirs, seed)
+    src = np.arange(n, dtype=np.int32) if sources is None else np.ascontiguousarray(sources, dtype=np.int32)
+    idx = np.empty((src.shape[0], num_dirs), dtype=np.int32)
+    amb = np.empty((src.shape[0], num_dirs), dtype=np.uint8)
+    mar = None if margins is None else np.array(margins, dtype=np.float64)
+    _lib().ora_index(ctypes.c_int(n), _p(means), _p(quats), _p(log_scales), _p(opacity), _p(normals),
+                     ctypes.c_int(num_dirs), _p(dirs), _p(_cut_array(cut)), ctypes.c_double(t_same), _p(mar),
+                     _p(src), ctypes.c_int(src.shape[0]), _p(idx), _p(amb), ctypes.c_int(threads or default_threads()))
+    return idx, amb.astype(bool)
+
+
+def self_transfer(scene, num_dirs, index, t_prev, seed=0, sources=None):
+    """One recursion step of the self-transfer (Eq. 32-34):
+    t[q, c, :] = (4 pi / S) sum_{s: idx >= 0} max(0, n_i . w_s) (rho_{j,c} / pi) t_prev[j, c', :]
+    with i = sources[q], j = index[q, s], c' = c for an RGB t_prev [n, 3, K] and
+    0 for a mono one [n, 1, K].  FP64."""
+    normals = _f64(scene["normals"])
+    albedo = _f64(scene["albedo"])
+    tp = _f64(t_prev)
+    n = normals.shape[0]
+    src = np.arange(n) if sources is None else np.asarray(sources)
+    dirs = directions(num_dirs, seed)
+    S = dirs.shape[0]
+    out = np.zeros((len(src), 3, tp.shape[2]))
+    for q, i in enumerate(src):
+        c = normals[i] @ dirs.T
+        for s in range(S):
+            j = int(index[q, s])
+            if j < 0 or not c[s] > 0.0:
+                continue
+            for ch in range(3):
+                out[q, ch] += (4.0 * math.pi / S) * c[s] * albedo[j, ch] / math.pi * tp[j, ch if tp.shape[1] == 3 else 0]
+    return out
+
+
+def index_transfer(scene, num_dirs, bands, bounces, seed=0, cut=None, t_same=1.0, threads=None):
+    """Total transfer of every splat with the paper's bounce (Eq. 35 with the
+    direct term, reading c14): sum_{m=0..bounces} T^m, T^0 the direct
+    transfer, T^m = self_transfer(T^{m-1}).  Returns dict(t=[n,3,K] (or
+    [n,1,K] for bounces = 0), index, amb, terms=[T^0, ..., T^bounces])."""
+    n = scene["means"].shape[0]
+    d = direct_transfer(scene, num_dirs, bands, seed, cut, threads=threads)["t"][:, None, :]
+    terms = [d]
+    if bounces == 0:
+        return dict(t=d, index=None, amb=None, terms=terms)
+    idx, amb = index_matrix(scene, num_dirs, seed, cut, t_same, threads=threads)
+    total = np.repeat(d, 3, axis=1)
+    prev = d
+    for _ in range(bounces):
+        prev = self_transfer(scene, num_dirs, idx, prev, seed)
+        terms.append(prev)
+        total = total + prev
+    return dict(t=total, index=idx, amb=amb, terms=terms)
 
 
 # ----------------------------------------------------------------------------

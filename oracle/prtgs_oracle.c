@@ -558,3 +558,89 @@ int ora_bounce(int n, const double* means, const double* quats, const double* lo
     free(g);
     return missing;
 }
+
+/* Index matrix of the paper's own bounce (Sec. 4.4: the weight of Eq. 26,
+ * the same-surface filter after Eq. 27, the argmax per direction): for each
+ * ray of the listed sources with c = n_i . w > 0, the hits are walked in
+ * (t*, j) order up to the one that takes the transmittance below T_eps; hit j
+ * is a candidate if the transmittance T_j in front of it is <= t_same, and
+ * weighs W_j = alpha_j T_j max(-w . n_j, 0).  idx = the candidate of largest
+ * W (the nearer one on a tie), or -1 when no candidate has W > 0 or the ray
+ * is not traced.  With `mar`, amb[q][s] = 1 where FP32 evaluation may pick
+ * differently: an ambiguous hit predicate or c, tied t*, T within its margin
+ * of T_eps or of t_same, a facing factor within mar[0] of 0, or a runner-up
+ * within 1e-4 (relative) of the best weight. */
+int ora_index(int n, const double* means, const double* quats, const double* log_scales, const double* opacity,
+              const double* normals, int S, const double* dirs, const double* cut, double t_same, const double* mar,
+              const int* sources, int count, int* idx_out, unsigned char* amb_out, int threads)
+{
+    OraGauss* g = ora_setup(n, means, quats, log_scales, opacity);
+    int nt = ora_threads(threads);
+#pragma omp parallel num_threads(nt)
+    {
+        OraHit* hits = (OraHit*)malloc(sizeof(OraHit) * (size_t)(n > 0 ? n : 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int q = 0; q < count; ++q) {
+            int i = sources[q];
+            const double* nrm = normals + 3 * (size_t)i;
+            for (int s = 0; s < S; ++s) {
+                const double* w = dirs + 3 * (size_t)s;
+                double c = dot3(nrm, w);
+                int amb = mar && fabs(c) <= mar[0];
+                int best = -1;
+                if (c > 0.0 || amb) {
+                    int nh = 0;
+                    for (int j = 0; j < n; ++j) {
+                        if (j == i) continue;
+                        double t, alpha;
+                        int a_j;
+                        int hit = ora_test(&g[j], g[i].mu, w, cut, mar, &t, &alpha, &a_j);
+                        if (hit || a_j) {
+                            hits[nh].t = t;
+                            hits[nh].alpha = hit ? alpha : -1.0;
+                            hits[nh].alpha_if_hit = alpha;
+                            hits[nh].j = j;
+                            hits[nh].amb = a_j;
+                            ++nh;
+                        }
+                    }
+                    qsort(hits, (size_t)nh, sizeof(OraHit), ora_hit_cmp);
+                    double T = 1.0, bestW = 0.0, second = 0.0;
+                    int in_front = 0;   /* hits multiplied into T so far (T = 1 exactly before any) */
+                    for (int h = 0; h < nh; ++h) {
+                        if (hits[h].amb) amb = 1;
+                        if (mar && h > 0 && fabs(hits[h].t - hits[h - 1].t) <= mar[4] * (1.0 + fabs(hits[h].t)))
+                            amb = 1;
+                        if (hits[h].alpha < 0.0) continue;
+                        double a = hits[h].alpha;
+                        if (mar && in_front && fabs(T - t_same) <= mar[3] * t_same) amb = 1;
+                        if (T <= t_same) {
+                            const double* nj = normals + 3 * (size_t)hits[h].j;
+                            double f = -dot3(w, nj);
+                            if (mar && fabs(f) <= mar[0]) amb = 1;
+                            double W = a * T * (f > 0.0 ? f : 0.0);
+                            if (W > bestW) {
+                                second = bestW;
+                                bestW = W;
+                                best = hits[h].j;
+                            } else if (W > second) {
+                                second = W;
+                            }
+                        }
+                        T *= 1.0 - a;
+                        ++in_front;
+                        if (mar && fabs(T - cut[2]) <= mar[3] * cut[2]) amb = 1;
+                        if (T < cut[2]) break;
+                    }
+                    if (mar && best >= 0 && bestW - second <= 1e-4 * bestW) amb = 1;
+                    if (!(c > 0.0)) best = -1;
+                }
+                idx_out[(size_t)q * S + s] = best;
+                if (amb_out) amb_out[(size_t)q * S + s] = (unsigned char)(amb != 0);
+            }
+        }
+        free(hits);
+    }
+    free(g);
+    return 0;
+}
