@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PRTGS_ABI_VERSION 1
+#define PRTGS_ABI_VERSION 2
 
 typedef enum {
     PRTGS_OK = 0,
@@ -52,6 +52,7 @@ typedef enum { PRTGS_F32 = 0, PRTGS_BF16 = 1, PRTGS_F16 = 2 } prtgs_dtype;
 #define PRTGS_FLAG_NONFINITE 0x1u       /* a non-finite value reached a kernel */
 #define PRTGS_FLAG_STACK_OVERFLOW 0x2u  /* BVH deeper than the traversal stack */
 #define PRTGS_FLAG_BAD_TREE 0x4u        /* malformed BVH (wrong buffer or n): traversal stopped */
+#define PRTGS_FLAG_BAD_INDEX 0x8u       /* an index-matrix entry outside [-1, n): skipped */
 
 /* The splats (Sec. 3.1, Eq. 1-2; normal Sec. 4.3; albedo Sec. 4.2).
  * Caller-owned, read-only during calls. */
@@ -62,7 +63,7 @@ typedef struct {
     const float* log_scales;   /* [n][3] log of the scales S of Eq. 2 */
     const float* opacity;      /* [n]    learned opacity, in (0, 1] */
     const float* normals;      /* [n][3] unit normals */
-    const float* albedo;       /* [n][3] diffuse albedo rho; needed only for bounces == 1 */
+    const float* albedo;       /* [n][3] diffuse albedo rho; needed only for bounces >= 1 */
 } prtgs_gaussians;
 
 /* Parameters of the transfer (Sec. 4.4-4.5).  The cutoffs are the reading of
@@ -74,13 +75,27 @@ typedef struct {
     int32_t num_dirs;          /* S directions per splat, 1 .. 65536 */
     int32_t sh_bands;          /* L bands, K = L*L coefficients; 1 .. 4 */
     uint64_t seed;             /* seed of the stratified direction jitter */
-    int32_t bounces;           /* 0 = direct transfer only, 1 = plus one interreflection bounce */
+    int32_t bounces;           /* interreflection bounces: 0 (direct transfer only), 1 with
+                                  PRTGS_BOUNCE_BLEND, 0 .. 8 with PRTGS_BOUNCE_INDEX */
     float sigma_cut;           /* 3.0 */
     float t_min;               /* 0.0 */
     float T_eps;               /* 1e-4 */
     float alpha_min;           /* 0.0 */
     float alpha_max;           /* 0.99 */
+    int32_t bounce_mode;       /* PRTGS_BOUNCE_BLEND or PRTGS_BOUNCE_INDEX */
+    float t_same;              /* index mode: hits with transmittance in front above it are not
+                                  candidates (same-surface filter); (0, 1], 1 = off */
 } prtgs_transfer_desc;
+
+/* How a bounce weighs the hits of a ray.
+ * BLEND: every hit front to back with weight alpha_j T_j (depth-ordered alpha
+ *   blend), one bounce.
+ * INDEX: the paper's own scheme (Sec. 4.4 Eq. 26, Sec. 4.5 Eq. 32-35): per ray
+ *   only the hit of largest W_j = alpha_j T_j max(-w . n_j, 0) among hits with
+ *   T_j <= t_same (an index matrix, -1 = none), with full weight; bounce m
+ *   gathers bounce m - 1 of the indexed splats, no re-tracing. */
+enum { PRTGS_BOUNCE_BLEND = 0, PRTGS_BOUNCE_INDEX = 1 };
+#define PRTGS_MAX_INDEX_BOUNCES 8
 
 /* Gradients (each pointer may be NULL = not wanted).  Accumulated (+=) into
  * caller-initialised buffers of the shapes of prtgs_gaussians. */
@@ -144,7 +159,10 @@ prtgs_status prtgs_bvh_leaf_order(const void* bvh, int32_t n, int32_t* order /* 
 /* alpha_j T_j with T_j the transmittance in front of it, until the         */
 /* transmittance drops below T_eps, and                                     */
 /*   transfer[i][c][:] = t_dir[i][:] + (4 pi/S) sum_s c sum_j w_j rho_jc/pi t_dir[j][:].*/
-/* transfer: [n][C][K], C = 1 (bounces 0) or 3 (bounces 1), written for the */
+/* With bounce_mode PRTGS_BOUNCE_INDEX the bounces follow the index matrix  */
+/* (see prtgs_index_matrix, prtgs_self_transfer):                           */
+/*   transfer[i][c][:] = t_dir[i][:] + sum_{m=1..bounces} T^m[i][c][:].     */
+/* transfer: [n][C][K], C = 1 (bounces 0) or 3 (bounces >= 1), written for the */
 /* selected sources only.  Sources are selected by leaf rank: those in     */
 /* leaf positions [first, first + count) (chunked or resumable runs; with  */
 /* bounces == 1 the range must be the whole scene).  vis (may be NULL):     */
@@ -158,6 +176,31 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g /* host */, cons
                                        const prtgs_transfer_desc* d /* host */, int32_t first,
                                        int32_t count, float* transfer, float* vis, void* ws,
                                        size_t ws_bytes, hipStream_t stream);
+
+/* Index matrix of the paper's bounce (Sec. 4.4, Eq. 26 and the same-surface */
+/* filter): index[i][s] = the Gaussian (original index) of largest           */
+/* W_j = alpha_j T_j max(-w_s . n_j, 0) along the ray of source i in          */
+/* direction s among the hits with T_j <= d->t_same, hits walked in (t*,     */
+/* leaf rank) order up to the one that takes the transmittance below T_eps   */
+/* (the nearer one on equal weights); -1 if no hit has W > 0 or c <= 0.      */
+/* Traces the direct pass first (its depths bound the walk).  index: [n][S] */
+/* int32, every source.  ws: prtgs_transfer_workspace_bytes of d with        */
+/* bounce_mode = PRTGS_BOUNCE_INDEX and bounces >= 1.                        */
+prtgs_status prtgs_index_matrix(const prtgs_gaussians* g /* host */, const void* bvh,
+                                const prtgs_transfer_desc* d /* host */, int32_t* index, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
+
+/* One step of the paper's recursive self-transfer (Sec. 4.5 Eq. 32-34):     */
+/*   t_out[i][c][k] = (4 pi / S) sum_{s: index[i][s] >= 0, c_is > 0}          */
+/*                    c_is (albedo[j][c] / pi) t_prev[j][c'][k],              */
+/* j = index[i][s], c_is = normals[i] . dirs[s], c' = c if c_prev == 3 else  */
+/* 0.  dirs: [S][3] FP32 (prtgs_direction_table); normals, albedo [n][3];    */
+/* index [n][S]; t_prev [n][c_prev][K]; t_out [n][3][K] (overwritten; must  */
+/* not alias t_prev).  Index entries outside [-1, n) are skipped and set    */
+/* PRTGS_FLAG_BAD_INDEX in *flags (a device word; may be NULL).              */
+prtgs_status prtgs_self_transfer(int32_t n, int32_t S, int32_t K, const float* dirs, const float* normals,
+                                 const float* albedo, const int32_t* index, const float* t_prev,
+                                 int32_t c_prev, float* t_out, unsigned* flags, hipStream_t stream);
 
 /* Work statistics of the direct pass over the selected sources (nothing else
  * is written): stats[0] traced rays, stats[1] child-box tests and stats[2]

@@ -4,11 +4,12 @@ Hand-written HIP kernels for gfx950 behind a C ABI (``include/prtgs.h``,
 ``libprtgs.so``); this package is the thin Python binding.  Build the
 library with ``python -m paper_2408_03538_amd.build``.
 """
-from .api import (Bvh, Scene, TransferParams, Workspace, abi_version, build_bvh, check_flags, direction_table, pack,
-                  precompute_transfer, read_flags, relight, relight_backward, transfer_backward,
-                  traversal_stats)
+from .api import (Bvh, Scene, TransferParams, Workspace, abi_version, build_bvh, check_flags, direction_table,
+                  index_matrix, pack, precompute_transfer, read_flags, relight, relight_backward, self_transfer,
+                  transfer_backward, traversal_stats)
 from .autograd import PRTGSTransfer, transfer_and_relight
 
 __all__ = ["Bvh", "Scene", "TransferParams", "Workspace", "abi_version", "build_bvh", "check_flags",
-           "direction_table", "pack", "precompute_transfer", "read_flags", "relight", "relight_backward",
-           "transfer_backward", "traversal_stats", "PRTGSTransfer", "transfer_and_relight"]
+           "direction_table", "index_matrix", "pack", "precompute_transfer", "read_flags", "relight",
+           "relight_backward", "self_transfer", "transfer_backward", "traversal_stats", "PRTGSTransfer",
+           "transfer_and_relight"]

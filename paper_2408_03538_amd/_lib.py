@@ -13,6 +13,9 @@ DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 FLAG_NONFINITE = 0x1
 FLAG_STACK_OVERFLOW = 0x2
 FLAG_BAD_TREE = 0x4
+FLAG_BAD_INDEX = 0x8
+BOUNCE_BLEND = 0
+BOUNCE_INDEX = 1
 
 c_size_t = ctypes.c_size_t
 c_void_p = ctypes.c_void_p
@@ -30,7 +33,7 @@ class Gaussians(ctypes.Structure):
 class TransferDesc(ctypes.Structure):
     _fields_ = [("num_dirs", c_int32), ("sh_bands", c_int32), ("seed", c_uint64), ("bounces", c_int32),
                 ("sigma_cut", c_float), ("t_min", c_float), ("T_eps", c_float), ("alpha_min", c_float),
-                ("alpha_max", c_float)]
+                ("alpha_max", c_float), ("bounce_mode", c_int32), ("t_same", c_float)]
 
 
 class Grads(ctypes.Structure):
@@ -52,6 +55,10 @@ SIGNATURES = {
     "prtgs_transfer_workspace_bytes": (c_size_t, [ctypes.POINTER(TransferDesc), c_int32]),
     "prtgs_precompute_transfer": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, ctypes.POINTER(TransferDesc),
                                             c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "prtgs_index_matrix": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, ctypes.POINTER(TransferDesc), c_void_p,
+                                     c_void_p, c_size_t, c_void_p]),
+    "prtgs_self_transfer": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_int32, c_void_p, c_void_p, c_void_p]),
     "prtgs_traversal_stats": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, ctypes.POINTER(TransferDesc), c_int32,
                                         c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     "prtgs_pack": (c_int32, [c_int64, c_void_p, c_void_p, c_int32, c_void_p]),

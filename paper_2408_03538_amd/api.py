@@ -91,6 +91,8 @@ class TransferParams:
     T_eps: float = 1e-4
     alpha_min: float = 0.0
     alpha_max: float = 0.99
+    bounce_mode: str = "blend"     # "blend" (depth-ordered alpha blend, 1 bounce) or "index" (argmax, n bounces)
+    t_same: float = 1.0            # index mode: same-surface filter (1 = off)
 
     @property
     def K(self) -> int:
@@ -101,8 +103,9 @@ class TransferParams:
         return 3 if self.bounces else 1
 
     def c_struct(self) -> _lib.TransferDesc:
+        mode = {"blend": _lib.BOUNCE_BLEND, "index": _lib.BOUNCE_INDEX}[self.bounce_mode]
         return _lib.TransferDesc(self.num_dirs, self.sh_bands, self.seed, self.bounces, self.sigma_cut, self.t_min,
-                                 self.T_eps, self.alpha_min, self.alpha_max)
+                                 self.T_eps, self.alpha_min, self.alpha_max, mode, self.t_same)
 
     def cut(self) -> dict:
         return dict(sigma_cut=self.sigma_cut, t_min=self.t_min, T_eps=self.T_eps, alpha_min=self.alpha_min,
@@ -134,6 +137,8 @@ def check_flags(ws: torch.Tensor, what: str = "kernel"):
         raise RuntimeError(f"{what}: BVH deeper than the traversal stack")
     if f & _lib.FLAG_BAD_TREE:
         raise RuntimeError(f"{what}: malformed BVH (buffer built for another scene?)")
+    if f & _lib.FLAG_BAD_INDEX:
+        raise IndexError(f"{what}: an index-matrix entry lies outside [-1, n)")
 
 
 # ----------------------------------------------------------------------------
@@ -208,6 +213,52 @@ def precompute_transfer(scene: Scene, bvh: Bvh, params: TransferParams, first: i
     if check:
         check_flags(ws, "precompute_transfer")
     return (out, vis) if want_vis else out
+
+
+def index_matrix(scene: Scene, bvh: Bvh, params: TransferParams, workspace: Workspace | None = None,
+                 check: bool = False) -> torch.Tensor:
+    """The paper's index matrix [n, S] int32 (original indices, -1 = none)."""
+    lib = _lib.load()
+    n = scene.n
+    g = scene.c_struct()
+    d = params.c_struct()
+    d.bounce_mode = _lib.BOUNCE_INDEX
+    d.bounces = max(1, d.bounces)
+    wbytes = lib.prtgs_transfer_workspace_bytes(ctypes.byref(d), n)
+    if wbytes == 0:
+        raise _lib.PrtgsError(1, "invalid transfer parameters")
+    ws = (workspace or Workspace()).get(wbytes, scene.device)
+    idx = torch.empty((n, params.num_dirs), dtype=torch.int32, device=scene.device)
+    _lib.check(lib.prtgs_index_matrix(ctypes.byref(g), _ptr(bvh.buffer), ctypes.byref(d), _ptr(idx), _ptr(ws),
+                                      ws.numel(), _stream()))
+    if check:
+        check_flags(ws, "index_matrix")
+    return idx
+
+
+def self_transfer(scene: Scene, params: TransferParams, index: torch.Tensor, t_prev: torch.Tensor,
+                  out: torch.Tensor | None = None, check: bool = False) -> torch.Tensor:
+    """One step of the recursive self-transfer: [n, 3, K] from t_prev [n, 1 or 3, K]
+    and the index matrix [n, S] (Eq. 32-34)."""
+    lib = _lib.load()
+    n, S, K = scene.n, params.num_dirs, params.K
+    if index.shape != (n, S) or index.dtype != torch.int32:
+        raise ValueError("index must be int32 [n, num_dirs]")
+    if t_prev.dim() != 3 or t_prev.shape[0] != n or t_prev.shape[1] not in (1, 3) or t_prev.shape[2] != K:
+        raise ValueError("t_prev must be [n, 1 or 3, K]")
+    if scene.albedo is None:
+        raise ValueError("the self-transfer needs the albedo")
+    dirs = direction_table(S, params.seed, params.sh_bands)[2].contiguous()
+    tp = t_prev.to(F32).contiguous()
+    index = index.contiguous()
+    if out is None:
+        out = torch.empty((n, 3, K), dtype=F32, device=scene.device)
+    flags = torch.zeros(1, dtype=torch.int32, device=scene.device)
+    _lib.check(lib.prtgs_self_transfer(n, S, K, _ptr(dirs), _ptr(scene.normals), _ptr(scene.albedo), _ptr(index),
+                                       _ptr(tp), tp.shape[1], _ptr(out), _ptr(flags), _stream()))
+    if check and int(flags.item()) & _lib.FLAG_BAD_INDEX:
+        raise IndexError("self_transfer: an index-matrix entry lies outside [-1, n)")
+    return out
 
 
 def traversal_stats(scene: Scene, bvh: Bvh, params: TransferParams, first: int = 0, count: int | None = None,

@@ -58,7 +58,13 @@ prtgs_status check_desc(const prtgs_transfer_desc* d)
         return fail(PRTGS_ERR_INVALID_ARG, "num_dirs = %d outside [1, 65536]", d->num_dirs);
     if (d->sh_bands < 1 || d->sh_bands > 4)
         return fail(PRTGS_ERR_INVALID_ARG, "sh_bands = %d outside [1, 4]", d->sh_bands);
-    if (d->bounces != 0 && d->bounces != 1) return fail(PRTGS_ERR_INVALID_ARG, "bounces = %d not 0 or 1", d->bounces);
+    if (d->bounce_mode != PRTGS_BOUNCE_BLEND && d->bounce_mode != PRTGS_BOUNCE_INDEX)
+        return fail(PRTGS_ERR_INVALID_ARG, "bounce_mode = %d unknown", d->bounce_mode);
+    if (d->bounce_mode == PRTGS_BOUNCE_BLEND && d->bounces != 0 && d->bounces != 1)
+        return fail(PRTGS_ERR_INVALID_ARG, "bounces = %d: the blended bounce takes 0 or 1", d->bounces);
+    if (d->bounce_mode == PRTGS_BOUNCE_INDEX && (d->bounces < 0 || d->bounces > PRTGS_MAX_INDEX_BOUNCES))
+        return fail(PRTGS_ERR_INVALID_ARG, "bounces = %d outside [0, %d]", d->bounces, PRTGS_MAX_INDEX_BOUNCES);
+    if (!(d->t_same > 0.0f && d->t_same <= 1.0f)) return fail(PRTGS_ERR_INVALID_ARG, "t_same outside (0, 1]");
     if (!(d->sigma_cut > 0.0f && d->sigma_cut <= kBoxSigma))
         return fail(PRTGS_ERR_INVALID_ARG, "sigma_cut = %g outside (0, 3] (BVH boxes are 3-sigma)", d->sigma_cut);
     if (!std::isfinite(d->t_min) || d->t_min < 0.0f) return fail(PRTGS_ERR_INVALID_ARG, "t_min must be finite and >= 0");
@@ -71,7 +77,7 @@ prtgs_status check_desc(const prtgs_transfer_desc* d)
 }
 
 struct TransferWs {
-    size_t dirs, Y, dir_order, tdir, albedo, tcut, queue, hitkey, hitalpha, total;
+    size_t dirs, Y, dir_order, tdir, albedo, tcut, queue, hitkey, hitalpha, index, term0, term1, total;
 };
 
 TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
@@ -97,6 +103,14 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     if (d.bounces) off += align256((size_t)bounce_waves(n) * kHitList * 64 * 8);
     w.hitalpha = off;
     if (d.bounces) off += align256((size_t)bounce_waves(n) * kHitList * 64 * 4);
+    // index mode: the index matrix and two bounce terms [n][3][K] (ping-pong)
+    const bool idx = d.bounces && d.bounce_mode == PRTGS_BOUNCE_INDEX;
+    w.index = off;
+    if (idx) off += align256(sizeof(int32_t) * (size_t)n * (size_t)d.num_dirs);
+    w.term0 = off;
+    if (idx) off += align256(sizeof(float) * 3 * (size_t)K * (size_t)n);
+    w.term1 = off;
+    if (idx) off += align256(sizeof(float) * 3 * (size_t)K * (size_t)n);
     w.total = off;
     return w;
 }
@@ -194,20 +208,78 @@ size_t prtgs_transfer_workspace_bytes(const prtgs_transfer_desc* d, int32_t n)
     return transfer_ws_layout(*d, n).total;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Arguments of the transfer kernels for sources [first, first + count).
+TransferArgs transfer_args(const prtgs_gaussians* g, const void* bvh, const prtgs_transfer_desc* d, int first,
+                           int count, float* transfer, float* vis, char* w, const TransferWs& W)
+{
+    const int n = g->n;
+    const BvhLayout L = bvh_layout(n);
+    const char* b = static_cast<const char*>(bvh);
+    const bool bounce = d->bounces > 0;
+    TransferArgs a{};
+    a.nodes = reinterpret_cast<const Node*>(b + L.nodes);
+    a.prims = reinterpret_cast<const Prim*>(b + L.prims);
+    a.normals = reinterpret_cast<const float4*>(b + L.normals);
+    a.order = reinterpret_cast<const int32_t*>(b + L.order);
+    a.dirs = reinterpret_cast<const float*>(w + W.dirs);
+    a.Y = reinterpret_cast<const float*>(w + W.Y);
+    a.dir_order = reinterpret_cast<const int32_t*>(w + W.dir_order);
+    a.S = d->num_dirs;
+    a.K = d->sh_bands * d->sh_bands;
+    a.n = n;
+    a.first = first;
+    a.count = count;
+    a.channels = bounce ? 3 : 1;
+    a.hp = hit_params(*d);
+    a.transfer = transfer;
+    a.vis = vis;
+    a.tdir_sorted = bounce ? reinterpret_cast<float*>(w + W.tdir) : nullptr;
+    a.albedo = g->albedo;
+    a.albedo_sorted = bounce ? reinterpret_cast<float4*>(w + W.albedo) : nullptr;
+    a.tcut = bounce ? reinterpret_cast<float*>(w + W.tcut) : nullptr;
+    a.queue = bounce ? reinterpret_cast<unsigned*>(w + W.queue) : nullptr;
+    a.hitkey = bounce ? reinterpret_cast<uint64_t*>(w + W.hitkey) : nullptr;
+    a.hitalpha = bounce ? reinterpret_cast<float*>(w + W.hitalpha) : nullptr;
+    a.index = nullptr;
+    a.t_same = d->t_same;
+    a.G = group_size(count);
+    a.flags = reinterpret_cast<unsigned*>(w);
+    return a;
+}
+
+// Flag word cleared, direction and SH tables and the direction order built.
+hipError_t transfer_setup(const prtgs_transfer_desc* d, char* w, const TransferWs& W, hipStream_t stream)
+{
+    hipError_t e = fill_u32(reinterpret_cast<unsigned*>(w), 0u, 1, stream);
+    if (e == hipSuccess)
+        e = launch_direction_table(d->num_dirs, d->seed, d->sh_bands, nullptr, nullptr,
+                                   reinterpret_cast<float*>(w + W.dirs), reinterpret_cast<float*>(w + W.Y), stream);
+    if (e == hipSuccess) e = launch_direction_order(d->num_dirs, reinterpret_cast<int32_t*>(w + W.dir_order), stream);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
 prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g, const void* bvh, const prtgs_transfer_desc* d,
                                        int32_t first, int32_t count, float* transfer, float* vis, void* ws,
                                        size_t ws_bytes, hipStream_t stream)
 {
     prtgs_status st = check_desc(d);
     if (st != PRTGS_OK) return st;
-    st = check_gaussians(g, d->bounces == 1);
+    st = check_gaussians(g, d->bounces > 0);
     if (st != PRTGS_OK) return st;
     const int n = g->n;
     if (!bvh || !ws) return fail(PRTGS_ERR_INVALID_ARG, "bvh or workspace is NULL");
     if (!aligned256(bvh) || !aligned256(ws)) return fail(PRTGS_ERR_INVALID_ARG, "bvh and workspace must be 256-byte aligned");
     if (first < 0 || count < 0 || (int64_t)first + count > n)
         return fail(PRTGS_ERR_INVALID_ARG, "source range [%d, %d + %d) outside [0, %d)", first, first, count, n);
-    if (d->bounces == 1 && (first != 0 || count != n))
+    if (d->bounces > 0 && (first != 0 || count != n))
         return fail(PRTGS_ERR_INVALID_ARG, "a bounce needs every source's direct transfer: use first = 0, count = n");
     if (count > 0 && !transfer) return fail(PRTGS_ERR_INVALID_ARG, "transfer is NULL");
     TransferWs W = transfer_ws_layout(*d, n);
@@ -215,51 +287,81 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g, const void* bvh
         return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes, W.total);
 
     char* w = static_cast<char*>(ws);
-    unsigned* flags = reinterpret_cast<unsigned*>(w);
-    float* dirs = reinterpret_cast<float*>(w + W.dirs);
-    float* Y = reinterpret_cast<float*>(w + W.Y);
-    hipError_t e = fill_u32(flags, 0u, 1, stream);
-    if (e == hipSuccess)
-        e = launch_direction_table(d->num_dirs, d->seed, d->sh_bands, nullptr, nullptr, dirs, Y, stream);
-    if (e == hipSuccess) e = launch_direction_order(d->num_dirs, reinterpret_cast<int32_t*>(w + W.dir_order), stream);
+    hipError_t e = transfer_setup(d, w, W, stream);
     if (e != hipSuccess) return hip_status(e, "direction table");
     if (count == 0) return ok();
-
-    const BvhLayout L = bvh_layout(n);
-    const char* b = static_cast<const char*>(bvh);
-    TransferArgs a{};
-    a.nodes = reinterpret_cast<const Node*>(b + L.nodes);
-    a.prims = reinterpret_cast<const Prim*>(b + L.prims);
-    a.normals = reinterpret_cast<const float4*>(b + L.normals);
-    a.order = reinterpret_cast<const int32_t*>(b + L.order);
-    a.dirs = dirs;
-    a.Y = Y;
-    a.dir_order = reinterpret_cast<const int32_t*>(w + W.dir_order);
-    a.S = d->num_dirs;
-    a.K = d->sh_bands * d->sh_bands;
-    a.n = n;
-    a.first = first;
-    a.count = count;
-    a.channels = d->bounces ? 3 : 1;
-    a.hp = hit_params(*d);
-    a.transfer = transfer;
-    a.vis = vis;
-    a.tdir_sorted = d->bounces ? reinterpret_cast<float*>(w + W.tdir) : nullptr;
-    a.albedo = g->albedo;
-    a.albedo_sorted = d->bounces ? reinterpret_cast<float4*>(w + W.albedo) : nullptr;
-    a.tcut = d->bounces ? reinterpret_cast<float*>(w + W.tcut) : nullptr;
-    a.queue = d->bounces ? reinterpret_cast<unsigned*>(w + W.queue) : nullptr;
-    a.hitkey = d->bounces ? reinterpret_cast<uint64_t*>(w + W.hitkey) : nullptr;
-    a.hitalpha = d->bounces ? reinterpret_cast<float*>(w + W.hitalpha) : nullptr;
-    a.G = group_size(count);
-    a.flags = flags;
+    TransferArgs a = transfer_args(g, bvh, d, first, count, transfer, vis, w, W);
     e = launch_transfer_direct(a, stream);
     if (e != hipSuccess) return hip_status(e, "direct transfer");
-    if (d->bounces) {
+    if (d->bounces > 0 && d->bounce_mode == PRTGS_BOUNCE_BLEND) {
         e = launch_transfer_bounce(a, stream);
         if (e != hipSuccess) return hip_status(e, "bounce transfer");
+    } else if (d->bounces > 0) {
+        a.index = reinterpret_cast<int32_t*>(w + W.index);
+        e = launch_transfer_index(a, stream);
+        if (e != hipSuccess) return hip_status(e, "index matrix");
+        // T^m from T^(m-1) by gathers; T^0 is the direct transfer the output
+        // already holds in all three channels
+        const int K = a.K;
+        float* terms[2] = {reinterpret_cast<float*>(w + W.term0), reinterpret_cast<float*>(w + W.term1)};
+        const float* prev = transfer;
+        for (int m = 1; m <= d->bounces; ++m) {
+            float* out = terms[(m - 1) % 2];
+            e = launch_self_transfer(n, a.S, K, a.dirs, g->normals, g->albedo, a.index, prev, 3, out, a.flags, stream);
+            if (e == hipSuccess) e = launch_add(transfer, out, (size_t)n * 3 * K, stream);
+            if (e != hipSuccess) return hip_status(e, "self-transfer");
+            prev = out;
+        }
     }
     return ok();
+}
+
+prtgs_status prtgs_index_matrix(const prtgs_gaussians* g, const void* bvh, const prtgs_transfer_desc* d,
+                                int32_t* index, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    prtgs_status st = check_desc(d);
+    if (st != PRTGS_OK) return st;
+    st = check_gaussians(g, false);
+    if (st != PRTGS_OK) return st;
+    const int n = g->n;
+    if (!bvh || !ws || !index) return fail(PRTGS_ERR_INVALID_ARG, "bvh, index or workspace is NULL");
+    if (!aligned256(bvh) || !aligned256(ws)) return fail(PRTGS_ERR_INVALID_ARG, "bvh and workspace must be 256-byte aligned");
+    // the workspace of the index mode with at least one bounce
+    prtgs_transfer_desc di = *d;
+    di.bounce_mode = PRTGS_BOUNCE_INDEX;
+    if (di.bounces < 1) di.bounces = 1;
+    TransferWs W = transfer_ws_layout(di, n);
+    if (ws_bytes < W.total)
+        return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes, W.total);
+    char* w = static_cast<char*>(ws);
+    hipError_t e = transfer_setup(&di, w, W, stream);
+    if (e != hipSuccess) return hip_status(e, "direction table");
+    // direct pass into scratch (its per-ray depths bound the walk), then the walk
+    TransferArgs a = transfer_args(g, bvh, &di, 0, n, reinterpret_cast<float*>(w + W.term0), nullptr, w, W);
+    a.channels = 1;
+    a.tdir_sorted = nullptr;   // the walk needs neither the sorted transfers nor the albedo
+    a.albedo = nullptr;
+    a.albedo_sorted = nullptr;
+    e = launch_transfer_direct(a, stream);
+    if (e != hipSuccess) return hip_status(e, "direct transfer");
+    a.index = index;
+    return hip_status(launch_transfer_index(a, stream), "index matrix");
+}
+
+prtgs_status prtgs_self_transfer(int32_t n, int32_t S, int32_t K, const float* dirs, const float* normals,
+                                 const float* albedo, const int32_t* index, const float* t_prev, int32_t c_prev,
+                                 float* t_out, unsigned* flags, hipStream_t stream)
+{
+    if (n < 0) return fail(PRTGS_ERR_INVALID_ARG, "n < 0");
+    if (S < 1 || S > 65536) return fail(PRTGS_ERR_INVALID_ARG, "S = %d outside [1, 65536]", S);
+    if (K != 1 && K != 4 && K != 9 && K != 16) return fail(PRTGS_ERR_INVALID_ARG, "K = %d not 1, 4, 9 or 16", K);
+    if (c_prev != 1 && c_prev != 3) return fail(PRTGS_ERR_INVALID_ARG, "c_prev = %d not 1 or 3", c_prev);
+    if (n == 0) return ok();
+    if (!dirs || !normals || !albedo || !index || !t_prev || !t_out)
+        return fail(PRTGS_ERR_INVALID_ARG, "a self-transfer pointer is NULL");
+    if (t_out == t_prev) return fail(PRTGS_ERR_INVALID_ARG, "t_out must not alias t_prev");
+    return hip_status(launch_self_transfer(n, S, K, dirs, normals, albedo, index, t_prev, c_prev, t_out, flags, stream),
+                      "self-transfer");
 }
 
 prtgs_status prtgs_traversal_stats(const prtgs_gaussians* g, const void* bvh, const prtgs_transfer_desc* d,

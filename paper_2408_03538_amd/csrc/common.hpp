@@ -148,11 +148,18 @@ struct TransferArgs {
     float* tcut;            // [count][S] direction-order position: depth of the
                             // farthest hit the direct pass used before the ray
                             // turned opaque (+inf if it never did), or null
+    int32_t* index;         // index mode: [n][S] argmax hit (original index), or null
+    float t_same;           // index mode: same-surface filter threshold
     int G;                  // sources per wave (group split); 1 = fan kernel
     unsigned* flags;
 };
 hipError_t launch_transfer_direct(const TransferArgs& a, hipStream_t stream, unsigned long long* stats = nullptr);
 hipError_t launch_transfer_bounce(const TransferArgs& a, hipStream_t stream);
+hipError_t launch_transfer_index(const TransferArgs& a, hipStream_t stream);
+hipError_t launch_self_transfer(int n, int S, int K, const float* dirs, const float* normals, const float* albedo,
+                                const int32_t* index, const float* t_prev, int c_prev, float* t_out, unsigned* flags,
+                                hipStream_t stream);
+hipError_t launch_add(float* acc, const float* x, size_t count, hipStream_t stream);
 // Persistent waves of the bounce launch for n sources (any group size): the
 // hit-list scratch holds this many waves.
 inline int bounce_waves(int n) { return n < kBounceWaves ? n : kBounceWaves; }

@@ -301,7 +301,11 @@ constexpr int kBlend = 8;   // hits selected per pass over the list
 constexpr int kScan = 8;    // list entries loaded together
 constexpr int kCheck = 8;   // depth checkpoints per ray and round
 
-template <int K>
+// kIndex: the paper's own bounce instead of the blend -- the same walk, but
+// each ray records the hit of largest alpha_j T_j max(-w . n_j, 0) among the
+// hits with T_j <= t_same (the nearer one on equal weights) in the index
+// matrix (-1: none, or not traced), and nothing is accumulated.
+template <int K, bool kIndex>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void bounce_kernel(TransferArgs a)
 {
     constexpr int M = kHitList;
@@ -344,13 +348,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
             const RayDir d = make_dir(a.dirs[3 * s], a.dirs[3 * s + 1], a.dirs[3 * s + 2]);
             const float c = nrm.x * d.wx + nrm.y * d.wy + nrm.z * d.wz;
             bool pending = valid && inrange && c > 0.0f;
+            if (kIndex && valid && inrange && !pending) a.index[(size_t)orig * a.S + s] = -1;
             if (__ballot(pending) == 0ull) continue;
+            const bool traced = pending;
             const BatchDir bd = batch_dir(d, pending);
             const float wc = c * kInvPi;
             // No hit beyond tc can carry weight: the direct pass saw the
             // transmittance fall below T_eps using hits no farther than tc.
             const float tc = pending ? a.tcut[(size_t)local * a.S + pos] : 0.0f;
             float T = 1.0f;
+            float bestW = 0.0f;   // (kIndex) largest weight so far and its leaf rank
+            int bestr = -1;
             bool started = false;
             uint64_t k_last = 0;   // key of the last blended hit (once started)
             int rounds = 0;
@@ -492,7 +500,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                         // one hit's loads at a time: hoisting all of them would
                         // hold kBlend (K + 4) registers at once
                         asm volatile("" ::: "memory");
-                        if (more && !done && bk[q] != kNoHit) {
+                        if (kIndex && more && !done && bk[q] != kNoHit) {
+                            const int r = key_j(bk[q]);
+                            if (T <= a.t_same) {
+                                const float4 nj = a.normals[r];
+                                const float f = -(d.wx * nj.x + d.wy * nj.y + d.wz * nj.z);
+                                const float W = ba[q] * T * fmaxf(f, 0.0f);
+                                if (W > bestW) {
+                                    bestW = W;
+                                    bestr = r;
+                                }
+                            }
+                            T *= 1.0f - ba[q];
+                            k_last = bk[q];
+                            started = true;
+                            ++got;
+                            if (T < hp.T_eps) done = true;
+                        } else if (!kIndex && more && !done && bk[q] != kNoHit) {
                             const int r = key_j(bk[q]);
                             const float w = ba[q] * T * wc;
                             const float4 rho = a.albedo_sorted[r];
@@ -533,19 +557,79 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 // Add this round to the source's transfer (the D lanes of a
                 // source summed first), so that the sums are dead during the
                 // next traversal.
+                if constexpr (!kIndex) {
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    float* out = a.transfer + ((size_t)orig * 3 + ch) * K;
+                    for (int ch = 0; ch < 3; ++ch) {
+                        float* out = a.transfer + ((size_t)orig * 3 + ch) * K;
 #pragma unroll
-                    for (int k = 0; k < K; ++k) {
-                        const float v = segment_sum(acc[ch][k], D) * scale;
-                        if (valid && (lane % D) == 0) out[k] += v;
-                        acc[ch][k] = 0.0f;
+                        for (int k = 0; k < K; ++k) {
+                            const float v = segment_sum(acc[ch][k], D) * scale;
+                            if (valid && (lane % D) == 0) out[k] += v;
+                            acc[ch][k] = 0.0f;
+                        }
                     }
                 }
             }
+            if (kIndex && traced) a.index[(size_t)orig * a.S + s] = bestr >= 0 ? a.order[bestr] : -1;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// the paper's recursive self-transfer: one gather step over the index matrix
+// (one wave per source, lanes over directions, then a wave reduction)
+// ---------------------------------------------------------------------------
+template <int K, int CP>
+__global__ __launch_bounds__(kBlock) void self_transfer_kernel(int n, int S, const float* __restrict__ dirs,
+                                                               const float* __restrict__ normals,
+                                                               const float* __restrict__ albedo,
+                                                               const int32_t* __restrict__ index,
+                                                               const float* __restrict__ t_prev,
+                                                               float* __restrict__ t_out, unsigned* flags)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int i = (blockIdx.x * kBlock + threadIdx.x) / kWave;   // source of this wave
+    if (i >= n) return;                                           // whole wave leaves together
+    const float nx = normals[3 * (size_t)i], ny = normals[3 * (size_t)i + 1], nz = normals[3 * (size_t)i + 2];
+    float acc[3][K];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[ch][k] = 0.0f;
+    for (int s0 = 0; s0 < S; s0 += kWave) {
+        const int s = s0 + lane;
+        if (s >= S) continue;
+        const int j = index[(size_t)i * S + s];
+        if (j < -1 || j >= n) {
+            if (flags) raise_flag(flags, PRTGS_FLAG_BAD_INDEX);
+            continue;
+        }
+        const float c = nx * dirs[3 * s] + ny * dirs[3 * s + 1] + nz * dirs[3 * s + 2];
+        if (j < 0 || !(c > 0.0f)) continue;
+        const float w = c * kInvPi;
+        const float r[3] = {albedo[3 * (size_t)j] * w, albedo[3 * (size_t)j + 1] * w, albedo[3 * (size_t)j + 2] * w};
+        const float* tp = t_prev + (size_t)j * CP * K;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[ch][k] = fmaf(r[ch], tp[(CP == 3 ? ch : 0) * K + k], acc[ch][k]);
+    }
+    const float scale = kFourPi / (float)S;
+    float mine = 0.0f;   // lane l < 3K ends up with element l
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float v = segment_sum(acc[ch][k], kWave);
+            mine = lane == ch * K + k ? v : mine;
+        }
+    if (lane < 3 * K) t_out[(size_t)i * 3 * K + lane] = mine * scale;
+}
+
+__global__ void add_kernel(float* __restrict__ acc, const float* __restrict__ x, size_t count)
+{
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
+        acc[e] += x[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -572,15 +656,15 @@ hipError_t launch_direct_k(const TransferArgs& a, unsigned long long* stats, hip
     return hipGetLastError();
 }
 
-template <int K>
+template <int K, bool kIndex>
 hipError_t launch_bounce_k(const TransferArgs& a, hipStream_t stream)
 {
     hipError_t e = fill_u32(a.queue, 0u, 1, stream);
     if (e != hipSuccess) return e;
     const int groups = (a.count + a.G - 1) / a.G;
     const int waves = groups < bounce_waves(a.n) ? groups : bounce_waves(a.n);   // the hit lists hold this many
-    hipLaunchKernelGGL(bounce_kernel<K>, dim3((waves + kBlock / kWave - 1) / (kBlock / kWave)), dim3(kBlock), 0,
-                       stream, a);
+    hipLaunchKernelGGL((bounce_kernel<K, kIndex>), dim3((waves + kBlock / kWave - 1) / (kBlock / kWave)),
+                       dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -602,12 +686,62 @@ hipError_t launch_transfer_bounce(const TransferArgs& a, hipStream_t stream)
 {
     if (a.count <= 0) return hipSuccess;
     switch (a.K) {
-        case 1: return launch_bounce_k<1>(a, stream);
-        case 4: return launch_bounce_k<4>(a, stream);
-        case 9: return launch_bounce_k<9>(a, stream);
-        case 16: return launch_bounce_k<16>(a, stream);
+        case 1: return launch_bounce_k<1, false>(a, stream);
+        case 4: return launch_bounce_k<4, false>(a, stream);
+        case 9: return launch_bounce_k<9, false>(a, stream);
+        case 16: return launch_bounce_k<16, false>(a, stream);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_transfer_index(const TransferArgs& a, hipStream_t stream)
+{
+    if (a.count <= 0) return hipSuccess;
+    switch (a.K) {
+        case 1: return launch_bounce_k<1, true>(a, stream);
+        case 4: return launch_bounce_k<4, true>(a, stream);
+        case 9: return launch_bounce_k<9, true>(a, stream);
+        case 16: return launch_bounce_k<16, true>(a, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int K>
+hipError_t launch_self_k(int n, int S, const float* dirs, const float* normals, const float* albedo,
+                         const int32_t* index, const float* t_prev, int c_prev, float* t_out, unsigned* flags,
+                         hipStream_t stream)
+{
+    const int blocks = (int)(((int64_t)n * kWave + kBlock - 1) / kBlock);
+    if (c_prev == 3)
+        hipLaunchKernelGGL((self_transfer_kernel<K, 3>), dim3(blocks), dim3(kBlock), 0, stream, n, S, dirs, normals,
+                           albedo, index, t_prev, t_out, flags);
+    else
+        hipLaunchKernelGGL((self_transfer_kernel<K, 1>), dim3(blocks), dim3(kBlock), 0, stream, n, S, dirs, normals,
+                           albedo, index, t_prev, t_out, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_self_transfer(int n, int S, int K, const float* dirs, const float* normals, const float* albedo,
+                                const int32_t* index, const float* t_prev, int c_prev, float* t_out, unsigned* flags,
+                                hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    switch (K) {
+        case 1: return launch_self_k<1>(n, S, dirs, normals, albedo, index, t_prev, c_prev, t_out, flags, stream);
+        case 4: return launch_self_k<4>(n, S, dirs, normals, albedo, index, t_prev, c_prev, t_out, flags, stream);
+        case 9: return launch_self_k<9>(n, S, dirs, normals, albedo, index, t_prev, c_prev, t_out, flags, stream);
+        case 16: return launch_self_k<16>(n, S, dirs, normals, albedo, index, t_prev, c_prev, t_out, flags, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_add(float* acc, const float* x, size_t count, hipStream_t stream)
+{
+    if (count == 0) return hipSuccess;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(add_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, acc, x, count);
+    return hipGetLastError();
 }
 
 }  // namespace prtgs

@@ -37,7 +37,7 @@ def test_binding_covers_the_header():
 
 
 def test_abi_version(lib):
-    assert lib.prtgs_abi_version() == 1
+    assert lib.prtgs_abi_version() == 2
 
 
 def test_size_queries(lib):
@@ -46,20 +46,23 @@ def test_size_queries(lib):
     small, big = lib.prtgs_bvh_bytes(1000), lib.prtgs_bvh_bytes(1_000_000)
     assert small >= 1000 * 64 + 999 * 64 and big > 100 * small
     assert lib.prtgs_build_workspace_bytes(1000) > 0
-    d = _lib.TransferDesc(64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99)
+    d = _lib.TransferDesc(64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0)
     assert lib.prtgs_transfer_workspace_bytes(ctypes.byref(d), 1000) > 64 * 4 * 12
-    bad = _lib.TransferDesc(64, 9, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99)
+    bad = _lib.TransferDesc(64, 9, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0)
     assert lib.prtgs_transfer_workspace_bytes(ctypes.byref(bad), 1000) == 0
     assert lib.prtgs_relight_backward_workspace_bytes(100, 16, 3, 64) > 0
 
 
 @pytest.mark.parametrize("desc,status", [
-    ((64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99), 1),     # NULL pointers in the scene
-    ((0, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99), 1),      # no directions
-    ((64, 5, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99), 1),     # too many bands
-    ((64, 3, 0, 2, 3.0, 0.0, 1e-4, 0.0, 0.99), 1),     # two bounces
-    ((64, 3, 0, 0, 4.0, 0.0, 1e-4, 0.0, 0.99), 1),     # cut-off beyond the 3-sigma boxes
-    ((64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 1.0), 1),      # alpha_max = 1
+    ((64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0), 1),     # NULL pointers in the scene
+    ((0, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0), 1),      # no directions
+    ((64, 5, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0), 1),     # too many bands
+    ((64, 3, 0, 2, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0), 1),     # two bounces
+    ((64, 3, 0, 0, 4.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0), 1),     # cut-off beyond the 3-sigma boxes
+    ((64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 1.0, 0, 1.0), 1),      # alpha_max = 1
+    ((64, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99, 2, 1.0), 1),     # unknown bounce mode
+    ((64, 3, 0, 9, 3.0, 0.0, 1e-4, 0.0, 0.99, 1, 1.0), 1),     # more than 8 index bounces
+    ((64, 3, 0, 2, 3.0, 0.0, 1e-4, 0.0, 0.99, 1, 0.0), 1),     # t_same = 0
 ])
 def test_transfer_validation(lib, desc, status):
     from paper_2408_03538_amd import _lib
@@ -94,7 +97,7 @@ def test_relight_validation(lib):
 def test_backward_rejects_bounce(lib):
     from paper_2408_03538_amd import _lib
     g = _lib.Gaussians(10, 256, 256, 256, 256, 256, 256)
-    d = _lib.TransferDesc(64, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99)
+    d = _lib.TransferDesc(64, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0)
     gr = _lib.Grads(None, None, None, None, None)
     st = lib.prtgs_transfer_backward(ctypes.byref(g), 256, ctypes.byref(d), 256, None, ctypes.byref(gr), 256, 1 << 30,
                                      None)
@@ -104,6 +107,23 @@ def test_backward_rejects_bounce(lib):
 def test_bounce_needs_whole_range(lib):
     from paper_2408_03538_amd import _lib
     g = _lib.Gaussians(10, 256, 256, 256, 256, 256, 256)
-    d = _lib.TransferDesc(64, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99)
+    d = _lib.TransferDesc(64, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0)
     st = lib.prtgs_precompute_transfer(ctypes.byref(g), 256, ctypes.byref(d), 2, 5, 256, None, 256, 1 << 30, None)
     assert st == 1
+
+
+def test_index_mode_workspace_grows(lib):
+    from paper_2408_03538_amd import _lib
+    blend = _lib.TransferDesc(64, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0)
+    index = _lib.TransferDesc(64, 3, 0, 3, 3.0, 0.0, 1e-4, 0.0, 0.99, 1, 1.0)
+    b = lib.prtgs_transfer_workspace_bytes(ctypes.byref(blend), 1000)
+    i = lib.prtgs_transfer_workspace_bytes(ctypes.byref(index), 1000)
+    assert i >= b + 1000 * 64 * 4 + 2 * 1000 * 3 * 9 * 4      # index matrix + two bounce terms
+
+
+def test_self_transfer_validation(lib):
+    assert lib.prtgs_self_transfer(10, 64, 5, 256, 256, 256, 256, 256, 1, 512, None, None) == 1   # K = 5
+    assert lib.prtgs_self_transfer(10, 64, 9, 256, 256, 256, 256, 256, 2, 512, None, None) == 1   # c_prev = 2
+    assert lib.prtgs_self_transfer(10, 64, 9, 256, 256, 256, 256, 256, 1, 256, None, None) == 1   # aliasing
+    assert lib.prtgs_self_transfer(10, 64, 9, None, 256, 256, 256, 256, 1, 512, None, None) == 1  # NULL
+    assert lib.prtgs_self_transfer(0, 64, 9, None, None, None, None, None, 1, None, None, None) == 0
