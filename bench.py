@@ -276,7 +276,33 @@ def bench_million(prt, torch, scenegen, np):
                          "algorithmic_bytes": round(b_ray, 1)},
              "direct_hbm_implied_frac": round(traced / (t_direct * 1e-3) * b_ray / 1e9 / PEAK_HBM_GBS, 4)}
     log(f"million: step {res['ms_step']:.0f} ms, direct {t_direct:.0f} ms")
-    del res, out
+    # the paper's own bounce: index matrix once, then n bounces by gathers
+    p_idx = prt.TransferParams(num_dirs=params.num_dirs, sh_bands=params.sh_bands, bounce_mode="index", bounces=3)
+    out3 = torch.zeros((sc.n, 3, params.K), dtype=torch.float32, device="cuda")
+    ws3 = prt.Workspace()
+    prt.precompute_transfer(sc, res["bvh"], p_idx, out=out3, workspace=ws3)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    prt.precompute_transfer(sc, res["bvh"], p_idx, out=out3, workspace=ws3)
+    ev[1].record()
+    idx = prt.index_matrix(sc, res["bvh"], p_idx, workspace=ws3)
+    ev[2].record()
+    prev = prt.self_transfer(sc, p_idx, idx, out3)
+    ev[3].record()
+    torch.cuda.synchronize()
+    t_all, t_idx, t_gather = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])
+    out_d["index_bounces"] = {
+        "workload": "million, the paper's bounce: index matrix + 3 bounces by gathers",
+        "ms_direct_plus_3_bounces": round(t_all, 2), "ms_direct_plus_index_matrix": round(t_idx, 2),
+        "ms_per_gather_bounce": round(t_gather, 3)}
+    # algorithmic bytes of one gather bounce: the index rows, normals and
+    # outputs, plus one RGB transfer row and albedo per indexed ray
+    nidx = int((idx >= 0).sum().item())
+    g_bytes = sc.n * (4 * params.num_dirs + 12 + 12 * params.K) + nidx * (12 * params.K + 12)
+    out_d["index_bounces"]["indexed_rays"] = nidx
+    out_d["index_bounces"]["gather_GBps"] = round(g_bytes / (t_gather * 1e-3) / 1e9, 1)
+    log(f"million index mode: direct + index + 3 bounces {t_all:.0f} ms, one gather bounce {t_gather:.2f} ms")
+    del res, out, out3, ws3, idx, prev
     torch.cuda.empty_cache()
     return out_d
 

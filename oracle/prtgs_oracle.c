@@ -566,10 +566,17 @@ int ora_bounce(int n, const double* means, const double* quats, const double* lo
  * is a candidate if the transmittance T_j in front of it is <= t_same, and
  * weighs W_j = alpha_j T_j max(-w . n_j, 0).  idx = the candidate of largest
  * W (the nearer one on a tie), or -1 when no candidate has W > 0 or the ray
- * is not traced.  With `mar`, amb[q][s] = 1 where FP32 evaluation may pick
- * differently: an ambiguous hit predicate or c, tied t*, T within its margin
- * of T_eps or of t_same, a facing factor within mar[0] of 0, or a runner-up
- * within 1e-4 (relative) of the best weight. */
+ * is not traced.
+ * With `mar`, amb[q][s] = 1 where FP32 evaluation may pick differently.  A
+ * hit whose predicate lies within its margin (or two hits with tied t*) may
+ * or may not scale the T of every later hit by (1 - alpha): two candidates'
+ * weights then move against each other by at most the alphas of such hits
+ * lying between them, delta = 1e-4 + that sum.  The ray is ambiguous if a
+ * candidate other than the best lies within 2 delta of the best weight, if a
+ * hit whose candidacy is uncertain (its predicate, its T against t_same or
+ * its facing factor within the margins) could reach the best, if the walk
+ * may stop one hit later (T within its margin of T_eps) while the best weight
+ * is below 2 T_eps, or if c itself is within its margin of 0. */
 int ora_index(int n, const double* means, const double* quats, const double* log_scales, const double* opacity,
               const double* normals, int S, const double* dirs, const double* cut, double t_same, const double* mar,
               const int* sources, int count, int* idx_out, unsigned char* amb_out, int threads)
@@ -578,7 +585,11 @@ int ora_index(int n, const double* means, const double* quats, const double* log
     int nt = ora_threads(threads);
 #pragma omp parallel num_threads(nt)
     {
-        OraHit* hits = (OraHit*)malloc(sizeof(OraHit) * (size_t)(n > 0 ? n : 1));
+        size_t cap = (size_t)(n > 0 ? n : 1);
+        OraHit* hits = (OraHit*)malloc(sizeof(OraHit) * cap);
+        double* pa = (double*)malloc(sizeof(double) * (cap + 1));   /* uncertain alpha in front of position h */
+        double* cw = (double*)malloc(sizeof(double) * cap);         /* candidate weights by position */
+        unsigned char* cu = (unsigned char*)malloc(cap);            /* candidacy uncertain */
 #pragma omp for schedule(dynamic, 1)
         for (int q = 0; q < count; ++q) {
             int i = sources[q];
@@ -598,41 +609,61 @@ int ora_index(int n, const double* means, const double* quats, const double* log
                         if (hit || a_j) {
                             hits[nh].t = t;
                             hits[nh].alpha = hit ? alpha : -1.0;
-                            hits[nh].alpha_if_hit = alpha;
+                            hits[nh].alpha_if_hit = hit ? alpha : ora_alpha_if_hit(&g[j], g[i].mu, w, cut);
                             hits[nh].j = j;
                             hits[nh].amb = a_j;
                             ++nh;
                         }
                     }
                     qsort(hits, (size_t)nh, sizeof(OraHit), ora_hit_cmp);
-                    double T = 1.0, bestW = 0.0, second = 0.0;
-                    int in_front = 0;   /* hits multiplied into T so far (T = 1 exactly before any) */
+                    double T = 1.0, bestW = 0.0;
+                    int best_pos = -1, in_front = 0, eps_amb = 0, walked = 0;
+                    pa[0] = 0.0;
                     for (int h = 0; h < nh; ++h) {
-                        if (hits[h].amb) amb = 1;
+                        walked = h + 1;
+                        double da = 0.0;
+                        if (mar && hits[h].amb) da += hits[h].alpha_if_hit;
                         if (mar && h > 0 && fabs(hits[h].t - hits[h - 1].t) <= mar[4] * (1.0 + fabs(hits[h].t)))
-                            amb = 1;
-                        if (hits[h].alpha < 0.0) continue;
+                            da += fmax(hits[h].alpha_if_hit, hits[h - 1].alpha_if_hit);
+                        pa[h + 1] = pa[h] + da;
+                        const double* nj = normals + 3 * (size_t)hits[h].j;
+                        const double f = -dot3(w, nj);
+                        const double fpos = f > 0.0 ? f : 0.0;
+                        cw[h] = 0.0;
+                        cu[h] = 0;
+                        if (hits[h].alpha < 0.0) {
+                            /* not a hit here, but it may be one in FP32 */
+                            cw[h] = hits[h].alpha_if_hit * T * fpos;
+                            cu[h] = 1;
+                            continue;
+                        }
                         double a = hits[h].alpha;
-                        if (mar && in_front && fabs(T - t_same) <= mar[3] * t_same) amb = 1;
-                        if (T <= t_same) {
-                            const double* nj = normals + 3 * (size_t)hits[h].j;
-                            double f = -dot3(w, nj);
-                            if (mar && fabs(f) <= mar[0]) amb = 1;
-                            double W = a * T * (f > 0.0 ? f : 0.0);
-                            if (W > bestW) {
-                                second = bestW;
-                                bestW = W;
-                                best = hits[h].j;
-                            } else if (W > second) {
-                                second = W;
-                            }
+                        int unc = hits[h].amb;
+                        if (mar && in_front && fabs(T - t_same) <= mar[3] * t_same) unc = 1;
+                        if (mar && fabs(f) <= mar[0]) unc = 1;
+                        double W = a * T * fpos;
+                        if (T <= t_same || unc) cw[h] = W;
+                        cu[h] = (unsigned char)unc;
+                        if (T <= t_same && W > bestW) {
+                            bestW = W;
+                            best = hits[h].j;
+                            best_pos = h;
                         }
                         T *= 1.0 - a;
                         ++in_front;
-                        if (mar && fabs(T - cut[2]) <= mar[3] * cut[2]) amb = 1;
+                        if (mar && fabs(T - cut[2]) <= mar[3] * cut[2]) eps_amb = 1;
                         if (T < cut[2]) break;
                     }
-                    if (mar && best >= 0 && bestW - second <= 1e-4 * bestW) amb = 1;
+                    if (mar) {
+                        for (int h = 0; h < walked; ++h) {
+                            if (h == best_pos && !cu[h]) continue;
+                            if (cw[h] <= 0.0) continue;
+                            int lo = h < best_pos ? h : best_pos, hi = h < best_pos ? best_pos : h;
+                            double delta = 1e-4 + (best_pos >= 0 ? pa[hi + 1] - pa[lo] : pa[h + 1]);
+                            if (cw[h] >= (1.0 - 2.0 * delta) * bestW) amb = 1;
+                        }
+                        if (eps_amb && bestW < 2.0 * cut[2]) amb = 1;
+                    }
                     if (!(c > 0.0)) best = -1;
                 }
                 idx_out[(size_t)q * S + s] = best;
@@ -640,6 +671,9 @@ int ora_index(int n, const double* means, const double* quats, const double* log
             }
         }
         free(hits);
+        free(pa);
+        free(cw);
+        free(cu);
     }
     free(g);
     return 0;
