@@ -89,11 +89,11 @@ def transfer_matrix(normal, rho, rough, metal, dirs, Y, vis, devc=None):
     vis[S] (read where n . w_s > 0).
 
     With `devc` [S] (a bound on |c_s| |V_fp32 - V| for each input ray, 0 for
-    clear rays), also returns the bound on t' from those rays and from the
-    directions within EPS_C of the horizon, where an FP32 evaluation may
-    count a term or not (input side: the term carries the factor c, so at
-    most EPS_C of it; output side: f stays finite there, the whole term), and
-    the matrix of |terms|, the scale of FP32 rounding."""
+    clear rays), also returns a bound on how far an FP32 evaluation may
+    legitimately land: from those rays, from the directions within EPS_C of
+    the horizon, where it may count a term or not (input side: the term
+    carries the factor c, so at most EPS_C of it; output side: f stays finite
+    there, the whole term), and from FP32 rounding; and the matrix of |terms|."""
     S, K = Y.shape
     wq = 4.0 * math.pi / S
     c = dirs @ normal
@@ -123,7 +123,13 @@ def transfer_matrix(normal, rho, rough, metal, dirs, Y, vis, devc=None):
     scale = np.zeros((3, K, K))
     if s_in.size:
         scale = wq * wq * np.einsum("sa,spc,pb->cab", np.abs(Ys), np.abs(T), np.abs(Ys))
-    return out, allow, scale
+    # FP32 evaluation: the half-vector terms are sums of products of unit
+    # vectors (absolute error a few eps) that the GGX lobe of width alpha
+    # amplifies by up to 1/alpha; the sums over s and p add about one eps
+    # per term summed
+    eps32 = 2.0 ** -24
+    fp32 = scale * (32 * eps32 * (1.0 + 1.0 / (rough * rough)) + (s_in.size + 16) * eps32)
+    return out, allow + fp32, scale
 
 
 def glossy_transfer(scene, num_dirs, bands, roughness, metallic, seed=0, sources=None, vis=None,
@@ -131,22 +137,24 @@ def glossy_transfer(scene, num_dirs, bands, roughness, metallic, seed=0, sources
     """t'[count, 3, K, K] of the listed sources (Eq. 36-41).  `vis` [count, S]
     overrides the traced visibility (entries for n . w <= 0 are not read).
     With `want_allow`, returns dict(t, allow, scale): allow bounds the change
-    an FP32 tracer's legitimately different V (rays within rounding of a cut)
-    and horizon decisions can make, scale is the matrix of |terms|."""
+    an FP32 evaluation can legitimately make (a tracer's different V on rays
+    within rounding of a cut, horizon decisions, rounding), scale is the
+    matrix of |terms|."""
     import oracle
     dirs, Y = oracle.tables(num_dirs, seed, bands)
     n = scene["means"].shape[0]
     src = np.arange(n) if sources is None else np.asarray(sources)
     devc = None
-    if vis is None or want_allow:
+    if vis is None:
         # per-direction V and its deviation bound: the direct transfer with an
         # identity basis gives (4 pi / S) V c per direction and (4 pi / S) |dev|
         r = oracle.direct_transfer(scene, num_dirs, num_dirs, seed, sources=src, want_vis=True,
                                    want_allow=want_allow, dirs=dirs, Y=np.eye(num_dirs))
-        if vis is None:
-            vis = r["vis"]
+        vis = r["vis"]
         if want_allow:
             devc = r["allow"] / (4.0 * math.pi / num_dirs)          # per ray c |dV| (+ |c| at the horizon)
+    elif want_allow:
+        devc = np.zeros((src.size, num_dirs))                        # the given V is exact for both sides
     vis = np.asarray(vis, dtype=np.float64)
     K = Y.shape[1]
     t = np.zeros((src.size, 3, K, K))
