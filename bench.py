@@ -13,6 +13,7 @@ baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
     python bench.py --copy-mib M      # plain device copy (counter calibration)
+    python bench.py --frame-only      # relit 1080p frames of the million-splat scene
 """
 from __future__ import annotations
 
@@ -70,6 +71,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle baseline budget")
     ap.add_argument("--copy-mib", type=int, default=0, help="only run a plain device copy of this size")
+    ap.add_argument("--frame-only", action="store_true",
+                    help="only time relit 1080p frames of the million-splat scene (synthetic transfers)")
     return ap.parse_args()
 
 
@@ -133,6 +136,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.frame_only:
+        frame_only(prt, torch, scenegen, np)
+        return
     log("generating the 100k surface workload")
     arr, sc, params, light = workload_setup(prt, torch, scenegen, "surface100k")
     n, S = sc.n, params.num_dirs
@@ -302,9 +308,58 @@ def bench_million(prt, torch, scenegen, np):
     out_d["index_bounces"]["indexed_rays"] = nidx
     out_d["index_bounces"]["gather_GBps"] = round(g_bytes / (t_gather * 1e-3) / 1e9, 1)
     log(f"million index mode: direct + index + 3 bounces {t_all:.0f} ms, one gather bounce {t_gather:.2f} ms")
-    del res, out, out3, ws3, idx, prev
+    del out3, ws3, idx, prev
+    out_d["frame_1080p"] = bench_frame(prt, torch, np, sc, res["transfer_out"], light)
+    del res, out
     torch.cuda.empty_cache()
     return out_d
+
+
+def frame_only(prt, torch, scenegen, np):
+    """Frames of the million-splat scene with synthetic RGB transfers (the
+    precompute's output has the same shape; the frame does not depend on
+    its values beyond the colours)."""
+    log("million-splat scene, synthetic transfers")
+    w = scenegen.workload("million")
+    sc = prt.Scene.from_arrays({k: np.asarray(v, dtype=np.float32) for k, v in w["scene"].items()})
+    t = torch.tensor(scenegen.synthetic_transfers(sc.n, w["bands"], 3, scenegen.SEED_SCENE + 2),
+                     dtype=torch.float32, device="cuda")
+    light = torch.tensor(w["light"], dtype=torch.float32, device="cuda")
+    print(json.dumps({"frame_1080p": bench_frame(prt, torch, np, sc, t, light)}), flush=True)
+
+
+def bench_frame(prt, torch, np, sc, transfer, light, frames=20):
+    """A relit frame at 1920 x 1080: relight every splat under one light
+    environment, then splat the colours (projection, tile binning, sort,
+    front-to-back blending).  Wall clock per frame includes the one host
+    synchronisation that reads the number of (Gaussian, tile) pairs."""
+    cam = prt.camera(prt.look_at((0.0, -5.5, 3.0), (0.0, 0.0, 0.8)), 1920, 1080, 50.0, 0.05)
+    light1 = light[:1].contiguous()
+    colours = torch.empty((sc.n, 1, 3), dtype=torch.float32, device="cuda")
+    ws = prt.Workspace()
+
+    def frame():
+        prt.relight(transfer, light1, out=colours)
+        return prt.splat_render(sc, colours[:, 0], cam, workspace=ws)
+
+    prt.relight(transfer, light1, out=colours)
+    _, T, inst = prt.splat_render(sc, colours[:, 0], cam, workspace=ws, want_T=True)
+    covered = float((T < 0.5).float().mean().item())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(frames):
+        img, _, _ = frame()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / frames
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    prt.relight(transfer, light1, out=colours)
+    b.record()
+    torch.cuda.synchronize()
+    log(f"1080p frame: {ms:.2f} ms ({1e3 / ms:.0f} fps), {inst} (Gaussian, tile) pairs")
+    return {"workload": "million-splat scene relit under one light, splatted at 1920x1080",
+            "ms_per_frame": round(ms, 3), "fps": round(1e3 / ms, 1), "ms_relight": round(a.elapsed_time(b), 4),
+            "gaussian_tile_pairs": inst, "covered_pixel_frac_T_below_half": round(covered, 3)}
 
 
 def bench_relight(prt, torch, scenegen, np, steps):

@@ -202,6 +202,71 @@ prtgs_status prtgs_self_transfer(int32_t n, int32_t S, int32_t K, const float* d
                                  const float* albedo, const int32_t* index, const float* t_prev,
                                  int32_t c_prev, float* t_out, unsigned* flags, hipStream_t stream);
 
+/* ---------------------------------------------------------------------- */
+/* Gaussian splatting of per-splat colours (the rasterizer the paper renders*/
+/* with, Sec. 3.1: Sigma = R S S^T R^T, footprint Sigma' = J W Sigma W^T J^T,*/
+/* front-to-back blending of Eq. 4), e.g. of prtgs_relight's colours.  With */
+/* x_c = view * [x; 1] (camera looks along +z), a Gaussian with x_c.z >=     */
+/* near_z projects to u = fx x/z + cx, v = fy y/z + cy with the 2D          */
+/* covariance J M diag(s^2) M^T J^T + 0.3 I (J the projection's Jacobian    */
+/* with x/z, y/z held within 1.3 x the frustum, M = view rotation x R(q)).   */
+/* Pixel (px, py) at (px + 0.5, py + 0.5) takes, in increasing camera depth */
+/* (then index), every Gaussian with alpha = min(0.99, o exp(-d^T Sigma'^-1 */
+/* d / 2)) >= 1/255, C += c alpha T, T *= 1 - alpha, and stops before the   */
+/* Gaussian that would take T below 1e-4; image = C + T background.          */
+typedef struct {
+    float view[12];            /* world-to-camera [R | t], row-major 3 x 4 */
+    float fx, fy, cx, cy;      /* intrinsics, pixels */
+    int32_t width, height;     /* image size, pixels (1 .. 16384) */
+    float near_z;              /* Gaussians nearer than this are culled (> 0) */
+    float background[3];
+} prtgs_camera;
+
+/* Workspace for n Gaussians and up to max_instances (Gaussian, tile) pairs. */
+size_t prtgs_splat_workspace_bytes(int32_t n, int32_t width, int32_t height, int64_t max_instances);
+/* colours: [n] RGB rows with colour_stride floats between rows (3 for an   */
+/* [n][3] array; 3B to pick one light of prtgs_relight's [n][B][3]).  image:*/
+/* [height][width][3] FP32; final_T: [height][width] or NULL.  Synchronises  */
+/* `stream` once, to read the number of (Gaussian, tile) pairs (returned in */
+/* *instances, host, may be NULL); more than max_instances (or 2^32) fails  */
+/* with PRTGS_ERR_WORKSPACE_TOO_SMALL and renders nothing.  Non-finite      */
+/* Gaussians set PRTGS_FLAG_NONFINITE and are skipped.                      */
+prtgs_status prtgs_splat_render(const prtgs_gaussians* g /* host */, const float* colours, int64_t colour_stride,
+                                const prtgs_camera* cam /* host */, float* image, float* final_T,
+                                int64_t max_instances, void* ws, size_t ws_bytes, int64_t* instances /* host */,
+                                hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/* Glossy transfer matrices (Sec. 4.5, Eq. 36-41) with the BRDF of Sec. 4.2: */
+/*   f(wi, wo) = (1 - m) rho / pi + D F G / (4 (wi . n)(wo . n)),           */
+/* D = GGX with alpha = r^2, F = Schlick with F0 = 0.04 (1 - m) + m rho,     */
+/* G = Smith with Schlick-GGX G1(x) = x / (x (1 - k) + k), k = (r + 1)^2 / 8 */
+/* (the paper leaves D, F, G to a supplement; these are the usual choices), */
+/* and with T(wi, wo) = f (wi . n) V(wi):                                     */
+/*   matrices[i][c][a][b] = (4 pi / S)^2 sum_s sum_p Y_a(w_s) T_c(w_s, w_p)  */
+/*                          Y_b(w_p)                                          */
+/* over the S stratified directions of d (seed, num_dirs <= 512, sh_bands 3  */
+/* or 4) as both input (s) and output (p) directions, T = 0 outside the     */
+/* upper hemisphere of the (normalised) normal.  The outgoing radiance of   */
+/* splat i seen from wo under light l is sum_b (sum_a l_a M[a][b]) Y_b(wo).  */
+/* roughness [n] in (0, 1], metallic [n] in [0, 1], albedo from g; vis:     */
+/* [n][S] per-ray visibility as written by prtgs_precompute_transfer (read  */
+/* where n . w > 0; negative entries count as 0).  matrices: [n][3][K][K]   */
+/* FP32, overwritten.  A splat with a zero or non-finite normal or material  */
+/* outside range gets zeros and sets PRTGS_FLAG_NONFINITE.                   */
+#define PRTGS_GLOSSY_MAX_DIRS 512
+size_t prtgs_glossy_workspace_bytes(const prtgs_transfer_desc* d /* host */);
+prtgs_status prtgs_glossy_transfer(const prtgs_gaussians* g /* host */, const float* roughness,
+                                   const float* metallic, const prtgs_transfer_desc* d /* host */,
+                                   const float* vis, float* matrices, void* ws, size_t ws_bytes,
+                                   hipStream_t stream);
+/* The per-frame view step: transfer[i][c][a] = sum_b matrices[i][c][a][b]  */
+/* Y_b(w_i), w_i = (eye - means[i]) / |eye - means[i]| (the basis in FP64),  */
+/* a transfer vector [n][3][K] that prtgs_relight turns into colours.       */
+/* eye: host float[3].  A splat at the eye gets zeros.                       */
+prtgs_status prtgs_glossy_view(int32_t n, int32_t K, const float* matrices, const float* means,
+                               const float* eye /* host */, float* transfer, hipStream_t stream);
+
 /* Work statistics of the direct pass over the selected sources (nothing else
  * is written): stats[0] traced rays, stats[1] child-box tests and stats[2]
  * Gaussian tests that a single-ray depth-first traversal of this BVH (same

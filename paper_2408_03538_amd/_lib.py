@@ -36,6 +36,11 @@ class TransferDesc(ctypes.Structure):
                 ("alpha_max", c_float), ("bounce_mode", c_int32), ("t_same", c_float)]
 
 
+class Camera(ctypes.Structure):
+    _fields_ = [("view", c_float * 12), ("fx", c_float), ("fy", c_float), ("cx", c_float), ("cy", c_float),
+                ("width", c_int32), ("height", c_int32), ("near_z", c_float), ("background", c_float * 3)]
+
+
 class Grads(ctypes.Structure):
     _fields_ = [("d_means", c_void_p), ("d_quats", c_void_p), ("d_log_scales", c_void_p),
                 ("d_opacity", c_void_p), ("d_normals", c_void_p)]
@@ -59,6 +64,15 @@ SIGNATURES = {
                                      c_void_p, c_size_t, c_void_p]),
     "prtgs_self_transfer": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_int32, c_void_p, c_void_p, c_void_p]),
+    "prtgs_glossy_workspace_bytes": (c_size_t, [ctypes.POINTER(TransferDesc)]),
+    "prtgs_glossy_transfer": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, c_void_p, ctypes.POINTER(TransferDesc),
+                                        c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "prtgs_glossy_view": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, ctypes.POINTER(c_float), c_void_p,
+                                    c_void_p]),
+    "prtgs_splat_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32, ctypes.c_int64]),
+    "prtgs_splat_render": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, ctypes.c_int64, ctypes.POINTER(Camera),
+                                     c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_size_t,
+                                     ctypes.POINTER(ctypes.c_int64), c_void_p]),
     "prtgs_traversal_stats": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, ctypes.POINTER(TransferDesc), c_int32,
                                         c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     "prtgs_pack": (c_int32, [c_int64, c_void_p, c_void_p, c_int32, c_void_p]),

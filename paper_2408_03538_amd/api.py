@@ -261,6 +261,109 @@ def self_transfer(scene: Scene, params: TransferParams, index: torch.Tensor, t_p
     return out
 
 
+def glossy_transfer(scene: Scene, params: TransferParams, vis: torch.Tensor, roughness: torch.Tensor,
+                    metallic: torch.Tensor, out: torch.Tensor | None = None, workspace: Workspace | None = None,
+                    check: bool = False) -> torch.Tensor:
+    """Glossy transfer matrices [n, 3, K, K] (see prtgs_glossy_transfer) from
+    the per-ray visibility of precompute_transfer(..., want_vis=True)."""
+    lib = _lib.load()
+    n, S, K = scene.n, params.num_dirs, params.K
+    if scene.albedo is None:
+        raise ValueError("glossy transfer needs the scene's albedo")
+    if vis.shape != (n, S) or vis.dtype != F32 or not vis.is_contiguous():
+        raise ValueError("vis must be contiguous float32 [n, S]")
+    for name, t in (("roughness", roughness), ("metallic", metallic)):
+        if t.shape != (n,) or t.dtype != F32 or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous float32 [n]")
+    g = scene.c_struct()
+    d = params.c_struct()
+    wbytes = lib.prtgs_glossy_workspace_bytes(ctypes.byref(d))
+    if wbytes == 0:
+        raise _lib.PrtgsError(1, "invalid glossy parameters (num_dirs <= 512, sh_bands 3 or 4)")
+    ws = (workspace or Workspace()).get(wbytes, scene.device)
+    if out is None:
+        out = torch.empty((n, 3, K, K), dtype=F32, device=scene.device)
+    _lib.check(lib.prtgs_glossy_transfer(ctypes.byref(g), _ptr(roughness), _ptr(metallic), ctypes.byref(d), _ptr(vis),
+                                         _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    if check:
+        check_flags(ws, "glossy_transfer")
+    return out
+
+
+def glossy_view(matrices: torch.Tensor, means: torch.Tensor, eye, out: torch.Tensor | None = None) -> torch.Tensor:
+    """The view step: transfer vectors [n, 3, K] of the matrices seen from
+    `eye` (per splat, the direction from its centre to the eye)."""
+    lib = _lib.load()
+    n, K = matrices.shape[0], matrices.shape[-1]
+    if matrices.shape != (n, 3, K, K) or matrices.dtype != F32 or not matrices.is_contiguous():
+        raise ValueError("matrices must be contiguous float32 [n, 3, K, K]")
+    if means.shape != (n, 3) or means.dtype != F32 or not means.is_contiguous():
+        raise ValueError("means must be contiguous float32 [n, 3]")
+    if out is None:
+        out = torch.empty((n, 3, K), dtype=F32, device=matrices.device)
+    e = (ctypes.c_float * 3)(*[float(v) for v in eye])
+    _lib.check(lib.prtgs_glossy_view(n, K, _ptr(matrices), _ptr(means), e, _ptr(out), _stream()))
+    return out
+
+
+def look_at(eye, target, up=(0.0, 0.0, 1.0)) -> list:
+    """World-to-camera [R | t] rows (12 floats) of a camera at `eye` looking
+    at `target` (camera +z forward, +y down in the image)."""
+    import numpy as np
+    eye, target, up = (np.asarray(v, dtype=np.float64) for v in (eye, target, up))
+    f = target - eye
+    f /= np.linalg.norm(f)
+    r = np.cross(f, up)
+    r /= np.linalg.norm(r)
+    d = np.cross(f, r)
+    R = np.stack([r, d, f])
+    t = -R @ eye
+    return [float(x) for x in np.concatenate([R, t[:, None]], axis=1).ravel()]
+
+
+def camera(view, width: int, height: int, fov_y_deg: float = 50.0, near_z: float = 0.05,
+           background=(0.0, 0.0, 0.0)) -> "_lib.Camera":
+    """A pinhole camera with the principal point at the image centre."""
+    import math
+    fy = 0.5 * height / math.tan(math.radians(fov_y_deg) / 2)
+    c = _lib.Camera()
+    for i, x in enumerate(view):
+        c.view[i] = x
+    c.fx, c.fy, c.cx, c.cy = fy, fy, 0.5 * width, 0.5 * height
+    c.width, c.height, c.near_z = width, height, near_z
+    for i in range(3):
+        c.background[i] = background[i]
+    return c
+
+
+def splat_render(scene: Scene, colours: torch.Tensor, cam, max_instances: int | None = None,
+                 workspace: Workspace | None = None, want_T: bool = False, check: bool = False):
+    """Render per-splat colours ([n, 3], or a [n, B, 3] relight output with
+    `colours[:, b]`) with Gaussian splatting.  Returns (image [H, W, 3],
+    final transmittance [H, W] or None, number of (Gaussian, tile) pairs)."""
+    lib = _lib.load()
+    n = scene.n
+    if colours.dim() != 2 or colours.shape[0] != n or colours.shape[1] != 3 or colours.dtype != F32:
+        raise ValueError("colours must be float32 [n, 3] (rows may be strided)")
+    if colours.stride(1) != 1:
+        raise ValueError("colour rows must be contiguous")
+    if max_instances is None:
+        max_instances = min(64 * n, 2**32 - 1)
+    g = scene.c_struct()
+    wbytes = lib.prtgs_splat_workspace_bytes(n, cam.width, cam.height, max_instances)
+    if wbytes == 0:
+        raise _lib.PrtgsError(1, "invalid splat parameters")
+    ws = (workspace or Workspace()).get(wbytes, scene.device)
+    image = torch.empty((cam.height, cam.width, 3), dtype=F32, device=scene.device)
+    T = torch.empty((cam.height, cam.width), dtype=F32, device=scene.device) if want_T else None
+    inst = ctypes.c_int64(0)
+    _lib.check(lib.prtgs_splat_render(ctypes.byref(g), _ptr(colours), colours.stride(0), ctypes.byref(cam), _ptr(image),
+                                      _ptr(T), max_instances, _ptr(ws), ws.numel(), ctypes.byref(inst), _stream()))
+    if check:
+        check_flags(ws, "splat_render")
+    return image, T, int(inst.value)
+
+
 def traversal_stats(scene: Scene, bvh: Bvh, params: TransferParams, first: int = 0, count: int | None = None,
                     workspace: Workspace | None = None) -> dict:
     """Single-ray work counts of the direct pass (see prtgs_traversal_stats)."""

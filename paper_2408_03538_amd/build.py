@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libprtgs.so")
-SOURCES = ["tables.hip", "bvh.hip", "transfer.hip", "backward.hip", "relight.hip", "capi.hip"]
+SOURCES = ["tables.hip", "bvh.hip", "transfer.hip", "backward.hip", "relight.hip", "splat.hip", "glossy.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -364,6 +364,190 @@ prtgs_status prtgs_self_transfer(int32_t n, int32_t S, int32_t K, const float* d
                       "self-transfer");
 }
 
+}  // extern "C"
+
+namespace {
+
+struct SplatWs {
+    size_t uv, conic_o, depth, rect, count, offset, total, ranges, keys, keys_alt, vals, vals_alt, scan, sort, end;
+    size_t scan_bytes, sort_bytes;
+};
+
+bool splat_ws_layout(int n, int width, int height, int64_t max_instances, SplatWs& w)
+{
+    const size_t ntiles = (size_t)((width + 15) / 16) * (size_t)((height + 15) / 16);
+    w.scan_bytes = splat_scan_temp_bytes(n);
+    w.sort_bytes = splat_sort_temp_bytes(max_instances > 0 ? max_instances : 1);
+    if (w.scan_bytes == 0 || w.sort_bytes == 0) return false;
+    size_t off = kFlagBytes;
+    auto take = [&](size_t& at, size_t bytes) {
+        at = off;
+        off += align256(bytes);
+    };
+    take(w.uv, 16 * (size_t)n);
+    take(w.conic_o, 16 * (size_t)n);
+    take(w.depth, 4 * (size_t)n);
+    take(w.rect, 16 * (size_t)n);
+    take(w.count, 4 * (size_t)n);
+    take(w.offset, 8 * (size_t)n);
+    take(w.total, 8);
+    take(w.ranges, 8 * ntiles);
+    take(w.keys, 8 * (size_t)max_instances);
+    take(w.keys_alt, 8 * (size_t)max_instances);
+    take(w.vals, 4 * (size_t)max_instances);
+    take(w.vals_alt, 4 * (size_t)max_instances);
+    take(w.scan, w.scan_bytes);
+    take(w.sort, w.sort_bytes);
+    w.end = off;
+    return true;
+}
+
+prtgs_status check_camera(const prtgs_camera* c)
+{
+    if (!c) return fail(PRTGS_ERR_INVALID_ARG, "camera is NULL");
+    if (c->width < 1 || c->width > 16384 || c->height < 1 || c->height > 16384)
+        return fail(PRTGS_ERR_INVALID_ARG, "image %d x %d outside [1, 16384]^2", c->width, c->height);
+    if (!(c->near_z > 0.0f) || !std::isfinite(c->near_z)) return fail(PRTGS_ERR_INVALID_ARG, "near_z must be > 0");
+    if (!(c->fx > 0.0f && c->fy > 0.0f) || !std::isfinite(c->fx) || !std::isfinite(c->fy) || !std::isfinite(c->cx) ||
+        !std::isfinite(c->cy))
+        return fail(PRTGS_ERR_INVALID_ARG, "intrinsics must be finite with fx, fy > 0");
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(c->view[i])) return fail(PRTGS_ERR_INVALID_ARG, "view matrix is not finite");
+    return PRTGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t prtgs_splat_workspace_bytes(int32_t n, int32_t width, int32_t height, int64_t max_instances)
+{
+    if (n < 1 || width < 1 || height < 1 || width > 16384 || height > 16384 || max_instances < 0 ||
+        max_instances > (int64_t)UINT32_MAX)
+        return 0;
+    SplatWs w;
+    if (!splat_ws_layout(n, width, height, max_instances, w)) return 0;
+    return w.end;
+}
+
+prtgs_status prtgs_splat_render(const prtgs_gaussians* g, const float* colours, int64_t colour_stride,
+                                const prtgs_camera* cam, float* image, float* final_T, int64_t max_instances,
+                                void* ws, size_t ws_bytes, int64_t* instances, hipStream_t stream)
+{
+    prtgs_status st = check_gaussians(g, false);
+    if (st != PRTGS_OK) return st;
+    st = check_camera(cam);
+    if (st != PRTGS_OK) return st;
+    if (!colours || !image || !ws) return fail(PRTGS_ERR_INVALID_ARG, "colours, image or workspace is NULL");
+    if (colour_stride < 3) return fail(PRTGS_ERR_INVALID_ARG, "colour_stride < 3");
+    if (!aligned256(ws)) return fail(PRTGS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (max_instances < 0 || max_instances > (int64_t)UINT32_MAX)
+        return fail(PRTGS_ERR_INVALID_ARG, "max_instances outside [0, 2^32)");
+    const int n = g->n;
+    SplatWs W;
+    if (!splat_ws_layout(n, cam->width, cam->height, max_instances, W))
+        return fail(PRTGS_ERR_HIP, "sort / scan size query failed");
+    if (ws_bytes < W.end)
+        return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes, W.end);
+    char* w = static_cast<char*>(ws);
+    SplatCamera c;
+    for (int i = 0; i < 12; ++i) c.view[i] = cam->view[i];
+    c.fx = cam->fx;
+    c.fy = cam->fy;
+    c.cx = cam->cx;
+    c.cy = cam->cy;
+    c.width = cam->width;
+    c.height = cam->height;
+    c.near_z = cam->near_z;
+    for (int i = 0; i < 3; ++i) c.background[i] = cam->background[i];
+    c.lim[0] = -1.3f * cam->cx / cam->fx;
+    c.lim[1] = 1.3f * ((float)cam->width - cam->cx) / cam->fx;
+    c.lim[2] = -1.3f * cam->cy / cam->fy;
+    c.lim[3] = 1.3f * ((float)cam->height - cam->cy) / cam->fy;
+    SplatBuffers b;
+    b.uv = reinterpret_cast<float4*>(w + W.uv);
+    b.conic_o = reinterpret_cast<float4*>(w + W.conic_o);
+    b.depth = reinterpret_cast<float*>(w + W.depth);
+    b.rect = reinterpret_cast<int4*>(w + W.rect);
+    b.count = reinterpret_cast<uint32_t*>(w + W.count);
+    b.offset = reinterpret_cast<uint64_t*>(w + W.offset);
+    b.total = reinterpret_cast<unsigned long long*>(w + W.total);
+    b.ranges = reinterpret_cast<uint2*>(w + W.ranges);
+    b.keys = reinterpret_cast<uint64_t*>(w + W.keys);
+    b.keys_alt = reinterpret_cast<uint64_t*>(w + W.keys_alt);
+    b.vals = reinterpret_cast<uint32_t*>(w + W.vals);
+    b.vals_alt = reinterpret_cast<uint32_t*>(w + W.vals_alt);
+    b.scan_temp = w + W.scan;
+    b.scan_temp_bytes = W.scan_bytes;
+    b.sort_temp = w + W.sort;
+    b.sort_temp_bytes = W.sort_bytes;
+    b.max_instances = max_instances;
+    b.flags = reinterpret_cast<unsigned*>(w);
+    hipError_t e = fill_u32(b.flags, 0u, 1, stream);
+    if (e == hipSuccess) e = launch_splat_front(n, c, g->means, g->quats, g->log_scales, g->opacity, b, stream);
+    if (e != hipSuccess) return hip_status(e, "splat projection");
+    unsigned long long total = 0;
+    e = hipMemcpyAsync(&total, b.total, sizeof(total), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_status(e, "splat instance count");
+    if (instances) *instances = (int64_t)total;
+    if ((int64_t)total > max_instances)
+        return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL, "%llu (Gaussian, tile) pairs, workspace holds %lld", total,
+                    (long long)max_instances);
+    return hip_status(launch_splat_back(n, c, (int64_t)total, colours, colour_stride, b, image, final_T, stream),
+                      "splat render");
+}
+
+size_t prtgs_glossy_workspace_bytes(const prtgs_transfer_desc* d)
+{
+    if (!d || d->num_dirs < 1 || d->num_dirs > PRTGS_GLOSSY_MAX_DIRS || (d->sh_bands != 3 && d->sh_bands != 4))
+        return 0;
+    const size_t S = (size_t)d->num_dirs, K = (size_t)d->sh_bands * d->sh_bands;
+    return kFlagBytes + align256(sizeof(float) * 3 * S) + align256(sizeof(float) * K * S);
+}
+
+prtgs_status prtgs_glossy_transfer(const prtgs_gaussians* g, const float* roughness, const float* metallic,
+                                   const prtgs_transfer_desc* d, const float* vis, float* matrices, void* ws,
+                                   size_t ws_bytes, hipStream_t stream)
+{
+    prtgs_status st = check_gaussians(g, true);
+    if (st != PRTGS_OK) return st;
+    if (!d) return fail(PRTGS_ERR_INVALID_ARG, "transfer desc is NULL");
+    if (d->num_dirs < 1 || d->num_dirs > PRTGS_GLOSSY_MAX_DIRS)
+        return fail(PRTGS_ERR_INVALID_ARG, "num_dirs = %d outside [1, %d]", d->num_dirs, PRTGS_GLOSSY_MAX_DIRS);
+    if (d->sh_bands != 3 && d->sh_bands != 4)
+        return fail(PRTGS_ERR_INVALID_ARG, "glossy matrices take sh_bands 3 or 4 (got %d)", d->sh_bands);
+    if (!roughness || !metallic || !vis || !matrices || !ws)
+        return fail(PRTGS_ERR_INVALID_ARG, "roughness, metallic, vis, matrices or workspace is NULL");
+    if (!aligned256(ws)) return fail(PRTGS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    const size_t need = prtgs_glossy_workspace_bytes(d);
+    if (ws_bytes < need) return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    const int S = d->num_dirs, K = d->sh_bands * d->sh_bands;
+    char* w = static_cast<char*>(ws);
+    unsigned* flags = reinterpret_cast<unsigned*>(w);
+    float* dirs = reinterpret_cast<float*>(w + kFlagBytes);
+    float* Y = reinterpret_cast<float*>(w + kFlagBytes + align256(sizeof(float) * 3 * (size_t)S));
+    hipError_t e = fill_u32(flags, 0u, 1, stream);
+    if (e == hipSuccess) e = launch_direction_table(S, d->seed, d->sh_bands, nullptr, nullptr, dirs, Y, stream);
+    if (e == hipSuccess)
+        e = launch_glossy(g->n, S, K, dirs, Y, g->normals, g->albedo, roughness, metallic, vis, matrices, flags,
+                          stream);
+    return hip_status(e, "glossy transfer");
+}
+
+prtgs_status prtgs_glossy_view(int32_t n, int32_t K, const float* matrices, const float* means, const float* eye,
+                               float* transfer, hipStream_t stream)
+{
+    if (n < 0) return fail(PRTGS_ERR_INVALID_ARG, "n < 0");
+    if (K != 9 && K != 16) return fail(PRTGS_ERR_INVALID_ARG, "K = %d not 9 or 16", K);
+    if (!eye) return fail(PRTGS_ERR_INVALID_ARG, "eye is NULL");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(eye[i])) return fail(PRTGS_ERR_INVALID_ARG, "eye is not finite");
+    if (n == 0) return ok();
+    if (!matrices || !means || !transfer) return fail(PRTGS_ERR_INVALID_ARG, "matrices, means or transfer is NULL");
+    return hip_status(launch_glossy_view(n, K, matrices, means, eye, transfer, stream), "glossy view");
+}
+
 prtgs_status prtgs_traversal_stats(const prtgs_gaussians* g, const void* bvh, const prtgs_transfer_desc* d,
                                    int32_t first, int32_t count, uint64_t* stats, void* ws, size_t ws_bytes,
                                    hipStream_t stream)

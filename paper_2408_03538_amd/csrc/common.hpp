@@ -178,6 +178,46 @@ struct BackwardArgs {
 };
 hipError_t launch_transfer_backward(const BackwardArgs& a, hipStream_t stream);
 
+// Gaussian splatting (splat.hip).
+struct SplatCamera {
+    float view[12];        // world to camera, rows of [R | t]
+    float fx, fy, cx, cy;
+    int width, height;
+    float near_z;
+    float background[3];
+    float lim[4];          // x/z and y/z bounds (1.3 x the frustum) for the projection Jacobian
+};
+struct SplatBuffers {
+    float4* uv;                // screen centre, cut on q, unused
+    float4* conic_o;
+    float* depth;
+    int4* rect;
+    uint32_t* count;
+    uint64_t* offset;
+    unsigned long long* total;
+    uint2* ranges;
+    uint64_t *keys, *keys_alt;
+    uint32_t *vals, *vals_alt;
+    void* scan_temp;
+    size_t scan_temp_bytes;
+    void* sort_temp;
+    size_t sort_temp_bytes;
+    int64_t max_instances;
+    unsigned* flags;
+};
+size_t splat_sort_temp_bytes(int64_t max_instances);
+size_t splat_scan_temp_bytes(int n);
+hipError_t launch_splat_front(int n, const SplatCamera& cam, const float* means, const float* quats,
+                              const float* log_scales, const float* opacity, const SplatBuffers& b, hipStream_t stream);
+hipError_t launch_splat_back(int n, const SplatCamera& cam, int64_t instances, const float* colours, int64_t stride,
+                             const SplatBuffers& b, float* image, float* final_T, hipStream_t stream);
+
+hipError_t launch_glossy(int n, int S, int K, const float* dirs, const float* Y, const float* normals,
+                         const float* albedo, const float* roughness, const float* metallic, const float* vis,
+                         float* out, unsigned* flags, hipStream_t stream);
+hipError_t launch_glossy_view(int n, int K, const float* M, const float* means, const float eye[3], float* z,
+                              hipStream_t stream);
+
 hipError_t launch_pack(int64_t count, const float* src, void* dst, prtgs_dtype dtype, hipStream_t stream);
 hipError_t launch_relight(int n, int K, int C, const void* T, prtgs_dtype tdt, int B, const float* L,
                           void* out, prtgs_dtype odt, hipStream_t stream);

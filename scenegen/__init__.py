@@ -231,6 +231,12 @@ def synthetic_transfers(n: int, bands: int, channels: int, seed: int) -> np.ndar
     return out
 
 
+def materials(n: int, seed: int) -> tuple:
+    """Glossy materials: roughness ~ U[0.1, 1], metallic ~ U[0, 1]."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.1, 1.0, n), rng.uniform(0.0, 1.0, n)
+
+
 def colour_targets(n: int, num_envs: int, seed: int) -> np.ndarray:
     """Loss targets C_hat [N, B, 3] ~ N(0, 1)."""
     return np.random.default_rng(seed).standard_normal((n, num_envs, 3))
@@ -247,6 +253,8 @@ WORKLOADS = {
     "million": "surface scene 200k + 20 shells x 40k = 1,000,000; S=512, 4 bands, RGB + one bounce",
     "relight3m": "3,000,000 synthetic RGB transfers, 16 coeffs, B=64 light environments",
     "grad200k": "surface scene N=200,000; S=256, 4 bands, direct; adjoint under an L2 loss",
+    "glossy100k": "surface scene N=100,000 with roughness U[0.1,1], metallic U[0,1]; S=256, 4 bands, "
+                  "glossy transfer matrices 3 x 16 x 16",
 }
 
 
@@ -267,4 +275,8 @@ def workload(name: str) -> dict:
     if name == "grad200k":
         return dict(scene=surface_scene(200_000, SEED_SCENE + 4), num_dirs=256, bands=4, bounces=0,
                     light=light_sh(1, 4, SEED_LIGHT + 4))
+    if name == "glossy100k":
+        rough, metal = materials(100_000, SEED_SCENE + 5)
+        return dict(scene=surface_scene(100_000, SEED_SCENE + 1), num_dirs=256, bands=4, bounces=0,
+                    roughness=rough, metallic=metal, light=light_sh(1, 4, SEED_LIGHT + 1))
     raise KeyError(name)

@@ -127,3 +127,52 @@ def test_self_transfer_validation(lib):
     assert lib.prtgs_self_transfer(10, 64, 9, 256, 256, 256, 256, 256, 1, 256, None, None) == 1   # aliasing
     assert lib.prtgs_self_transfer(10, 64, 9, None, 256, 256, 256, 256, 1, 512, None, None) == 1  # NULL
     assert lib.prtgs_self_transfer(0, 64, 9, None, None, None, None, None, 1, None, None, None) == 0
+
+
+def _camera(**kw):
+    from paper_2408_03538_amd import _lib
+    c = _lib.Camera()
+    for i, v in enumerate([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]):
+        c.view[i] = v
+    c.fx = c.fy = 100.0
+    c.cx, c.cy, c.width, c.height, c.near_z = 32.0, 24.0, 64, 48, 0.05
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def _gaussians(n=10):
+    from paper_2408_03538_amd import _lib
+    g = _lib.Gaussians()
+    g.n = n
+    for name in ("means", "quats", "log_scales", "opacity", "normals"):
+        setattr(g, name, 256)
+    return g
+
+
+@pytest.mark.parametrize("cam", [dict(width=0), dict(height=20000), dict(near_z=0.0), dict(fx=0.0),
+                                 dict(cy=float("nan"))])
+def test_splat_camera_validation(lib, cam):
+    img = ctypes.c_void_p(256)
+    assert lib.prtgs_splat_render(ctypes.byref(_gaussians()), 256, 3, ctypes.byref(_camera(**cam)), img, None,
+                                  100, 256, 1 << 20, None, None) == 1
+
+
+def test_splat_render_validation(lib):
+    g, c = _gaussians(), _camera()
+    nan_view = _camera()
+    nan_view.view[5] = float("inf")
+    call = lambda g=g, col=256, stride=3, cam=c, image=256, mi=100, ws=256: lib.prtgs_splat_render(
+        ctypes.byref(g), col, stride, ctypes.byref(cam), image, None, mi, ws, 1 << 20, None, None)
+    assert call(g=_gaussians(0)) == 1                 # no Gaussians
+    assert call(cam=nan_view) == 1                    # non-finite view
+    assert call(col=None) == 1
+    assert call(image=None) == 1
+    assert call(ws=None) == 1
+    assert call(stride=2) == 1                        # rows shorter than RGB
+    assert call(ws=512 + 8) == 1                      # workspace not 256-byte aligned
+    assert call(mi=-1) == 1
+    assert call(mi=1 << 32) == 1                      # pair index must fit 32 bits
+    assert lib.prtgs_splat_workspace_bytes(0, 64, 48, 100) == 0
+    assert lib.prtgs_splat_workspace_bytes(10, 0, 48, 100) == 0
+    assert lib.prtgs_splat_workspace_bytes(10, 64, 48, 1 << 32) == 0

@@ -1,0 +1,134 @@
+"""GPU parity of the glossy transfer matrices (Sec. 4.5, Eq. 36-41, BRDF of
+Sec. 4.2) and of the per-frame view step against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import scenegen
+from helpers import as_f32
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def prt():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2408_03538_amd as p
+    return p
+
+
+def _scene(seed, n_surface=1200, shells=2, per_shell=300):
+    sc = as_f32(scenegen._concat([scenegen.surface_scene(n_surface, seed), scenegen.shells(shells, per_shell, seed + 1)]))
+    n = sc["means"].shape[0]
+    rng = np.random.default_rng(seed + 2)
+    rough = rng.uniform(0.1, 1.0, n).astype(np.float32)
+    metal = rng.uniform(0.0, 1.0, n).astype(np.float32)
+    rough[:5] = [1.0, 0.1, 0.5, 0.05, 1.0]
+    metal[:5] = [0.0, 1.0, 0.0, 1.0, 1.0]
+    return sc, rough.astype(np.float64), metal.astype(np.float64)
+
+
+def _gpu_matrices(prt, scene, rough, metal, S, bands, vis=None):
+    import torch
+    sc = prt.Scene.from_arrays(scene)
+    params = prt.TransferParams(num_dirs=S, sh_bands=bands)
+    if vis is None:
+        bvh = prt.build_bvh(sc, check=True)
+        _, v = prt.precompute_transfer(sc, bvh, params, want_vis=True, check=True)
+    else:
+        v = torch.tensor(vis, dtype=torch.float32, device="cuda")
+    r = torch.tensor(rough, dtype=torch.float32, device="cuda")
+    m = torch.tensor(metal, dtype=torch.float32, device="cuda")
+    return prt.glossy_transfer(sc, params, v, r, m, check=True).cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("S,bands", [(64, 3), (128, 4), (256, 4)])
+def test_glossy_matrices_given_visibility(prt, oracle_mod, S, bands):
+    """Same visibility on both sides (the oracle's, rounded to FP32): the
+    matrices agree to FP32 rounding of the BRDF and the sums."""
+    from oracle import glossy
+    scene, rough, metal = _scene(91)
+    n = scene["means"].shape[0]
+    vis = oracle_mod.direct_transfer(scene, S, bands, want_vis=True)["vis"].astype(np.float32).astype(np.float64)
+    got = _gpu_matrices(prt, scene, rough, metal, S, bands, vis=vis)
+    src = np.concatenate([np.arange(8), np.random.default_rng(92).choice(np.arange(8, n), 120, replace=False)])
+    ref = glossy.glossy_transfer(scene, S, bands, rough, metal, sources=src, vis=vis[src], want_allow=True)
+    err = np.abs(got[src] - ref["t"])
+    bound = ref["allow"] + 1e-9             # same V on both sides: horizon decisions and FP32 rounding
+    assert (err <= bound).all(), f"max err/bound {np.max(err / bound):.2e}"
+    assert np.abs(ref["t"]).max() > 0.1
+    print(f"S={S} K={bands * bands}: max |d| {err.max():.2e}, max |d|/scale {np.max(err / (ref['scale'] + 1e-30)):.2e}, "
+          f"max |d|/bound {np.max(err / bound):.2e}")
+
+
+def test_glossy_end_to_end(prt, oracle_mod):
+    """Visibility traced on the GPU: within the oracle's bound for rays whose
+    cut-off decisions sit within FP32 rounding, plus FP32 rounding."""
+    from oracle import glossy
+    scene, rough, metal = _scene(93)
+    S, bands = 128, 4
+    n = scene["means"].shape[0]
+    got = _gpu_matrices(prt, scene, rough, metal, S, bands)
+    src = np.random.default_rng(94).choice(n, 100, replace=False)
+    ref = glossy.glossy_transfer(scene, S, bands, rough, metal, sources=src, want_allow=True)
+    err = np.abs(got[src] - ref["t"])
+    assert (err <= ref["allow"] + 1e-9).all()
+
+
+def test_glossy_view_and_relight(prt, oracle_mod):
+    """The view step (per splat Y(eye - mu), FP64 basis) and the relight of its
+    output against the oracle's basis and product."""
+    import torch
+    from oracle import glossy
+    scene, rough, metal = _scene(95, n_surface=500, shells=1, per_shell=200)
+    S, bands = 64, 4
+    n = scene["means"].shape[0]
+    vis = oracle_mod.direct_transfer(scene, S, bands, want_vis=True)["vis"].astype(np.float32).astype(np.float64)
+    M = _gpu_matrices(prt, scene, rough, metal, S, bands, vis=vis)
+    eye = np.array([0.3, -4.0, 2.5], dtype=np.float32)
+    Mt = torch.tensor(M, dtype=torch.float32, device="cuda")
+    means = torch.tensor(scene["means"], dtype=torch.float32, device="cuda")
+    z = prt.glossy_view(Mt, means, eye).cpu().numpy().astype(np.float64)
+    d = eye.astype(np.float64)[None, :] - scene["means"]
+    y = oracle_mod.sh_basis(bands, d)
+    ref = glossy.view_transfer(M, y)
+    scale = np.einsum("ncab,nb->nca", np.abs(M), np.abs(y))
+    assert (np.abs(z - ref) <= 2e-6 * scale + 1e-9).all()
+    light = scenegen.light_sh(8, bands, 5)
+    col = prt.relight(torch.tensor(z, dtype=torch.float32, device="cuda"),
+                      torch.tensor(light, dtype=torch.float32, device="cuda")).cpu().numpy()
+    ref_col = oracle_mod.relight(z.astype(np.float32).astype(np.float64), np.asarray(light, np.float32).astype(np.float64))
+    assert np.abs(col - ref_col).max() <= 2e-6 * np.abs(ref_col).max() + 1e-7
+
+
+def test_glossy_bad_material_is_flagged(prt):
+    import torch
+    scene, rough, metal = _scene(96, n_surface=200, shells=1, per_shell=50)
+    rough[3] = 0.0                      # roughness must be in (0, 1]
+    metal[7] = 1.5
+    sc = prt.Scene.from_arrays(scene)
+    params = prt.TransferParams(num_dirs=64, sh_bands=3)
+    vis = torch.ones((sc.n, 64), device="cuda")
+    r = torch.tensor(rough, dtype=torch.float32, device="cuda")
+    m = torch.tensor(metal, dtype=torch.float32, device="cuda")
+    with pytest.raises(FloatingPointError):
+        prt.glossy_transfer(sc, params, vis, r, m, check=True)
+    out = prt.glossy_transfer(sc, params, vis, r, m)
+    assert (out[3] == 0).all() and (out[7] == 0).all()
+    assert (out[4] != 0).any()
+
+
+def test_glossy_surface100k_sampled(prt, oracle_mod):
+    """The 100k surface scene at S = 256, 16 coefficients (the configuration
+    the benchmark times): 24 sampled splats end to end."""
+    from oracle import glossy
+    w = scenegen.workload("glossy100k")
+    scene = as_f32(w["scene"])
+    rough, metal = (np.asarray(w[k], np.float32).astype(np.float64) for k in ("roughness", "metallic"))
+    S, bands = w["num_dirs"], w["bands"]
+    got = _gpu_matrices(prt, scene, rough, metal, S, bands)
+    src = np.random.default_rng(97).choice(scene["means"].shape[0], 24, replace=False)
+    ref = glossy.glossy_transfer(scene, S, bands, rough, metal, sources=src, want_allow=True)
+    err = np.abs(got[src] - ref["t"])
+    assert (err <= ref["allow"] + 1e-9).all()
+    print(f"glossy100k: max |d| {err.max():.2e}")
