@@ -44,7 +44,7 @@ FLOPS_PER_PRIM_TEST = 70
 # counter runs (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy): see
 # profiles/direct_kernel_surface100k_hbm_counters.md.  Valid only for the
 # kernel sources it was measured on (hash below); null otherwise.
-MEASURED_TRAFFIC = {"sources_sha256_16": "25728a1f0eeeacda", "bytes_per_launch": 7.823e9}
+MEASURED_TRAFFIC = {"sources_sha256_16": "fd8d789ca0b5e920", "bytes_per_launch": 7.817e9}
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
                   "paper_2408_03538_amd/csrc/common.hpp"]
 
@@ -208,6 +208,7 @@ def main():
         result["million_bounce"] = bench_million(prt, torch, scenegen, np)
         result["relight_3m"] = bench_relight(prt, torch, scenegen, np, args.steps)
         result["backward_200k"] = bench_backward(prt, torch, scenegen, np, args.steps)
+        result["glossy_100k"] = bench_glossy(prt, torch, scenegen, np, args.steps)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(arr, params, args.cpu_seconds)
     print(json.dumps(result), flush=True)
@@ -413,6 +414,64 @@ def bench_relight(prt, torch, scenegen, np, steps):
     del T, T16, out32, out16
     torch.cuda.empty_cache()
     return res
+
+
+def bench_glossy(prt, torch, scenegen, np, steps):
+    """Glossy transfer matrices of the 100k surface scene (S = 256, 3 x 16 x 16
+    per splat) from the direct pass's visibilities, and the per-frame view +
+    relight of those matrices."""
+    log("glossy matrices: 100k x 256")
+    w = scenegen.workload("glossy100k")
+    arr = {k: np.asarray(v, dtype=np.float32) for k, v in w["scene"].items()}
+    sc = prt.Scene.from_arrays(arr)
+    params = prt.TransferParams(num_dirs=w["num_dirs"], sh_bands=w["bands"])
+    rough = torch.tensor(w["roughness"], dtype=torch.float32, device="cuda")
+    metal = torch.tensor(w["metallic"], dtype=torch.float32, device="cuda")
+    light = torch.tensor(w["light"], dtype=torch.float32, device="cuda")
+    bvh = prt.build_bvh(sc)
+    _, vis = prt.precompute_transfer(sc, bvh, params, want_vis=True)
+    ws = prt.Workspace()
+    M = prt.glossy_transfer(sc, params, vis, rough, metal, workspace=ws)
+    torch.cuda.synchronize()
+    reps = max(3, steps // 4)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        prt.glossy_transfer(sc, params, vis, rough, metal, out=M, workspace=ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    # the upper hemisphere of each normal, as the kernel lists it
+    dirs = prt.direction_table(params.num_dirs, 0, params.sh_bands)[2]
+    H = ((sc.normals @ dirs.T) > 0).sum(1).double()
+    Hp = torch.ceil(H / 16) * 16
+    # MFMA work: (Hp / 4) x (Hp / 16) 16x16x4 steps for U (two matrices), 4 per
+    # output block for the contraction over p; 2048 flops per 16x16x4
+    mfma_flops = float((2 * (Hp / 4) * (Hp / 16) * 2048 + 2 * 4 * (Hp / 16) * 2048).sum().item())
+    pairs = float((H * H).sum().item())
+    eye = (0.0, -5.5, 3.0)
+    z = prt.glossy_view(M, sc.means, eye)
+    col = prt.relight(z, light)
+    torch.cuda.synchronize()
+    c, d = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c.record()
+    for _ in range(10):
+        prt.glossy_view(M, sc.means, eye, out=z)
+        prt.relight(z, light, out=col)
+    d.record()
+    torch.cuda.synchronize()
+    ms_frame = c.elapsed_time(d) / 10
+    log(f"glossy: {ms:.2f} ms per 100k matrices, view + relight {ms_frame:.3f} ms")
+    out = {"workload": "glossy100k: surface scene N=100,000, S=256, 3 x 16 x 16 matrices, roughness U[0.1,1], "
+                       "metallic U[0,1]",
+           "ms_glossy_matrices": round(ms, 3), "matrices_per_s": round(sc.n / (ms * 1e-3), 1),
+           "brdf_pairs_per_s": round(pairs / (ms * 1e-3), 1),
+           "mfma_TFLOPs": round(mfma_flops / (ms * 1e-3) / 1e12, 2), "mfma_peak_fp32_TFLOPs": PEAK_FP32_TFLOPS,
+           "ms_view_plus_relight": round(ms_frame, 4),
+           "view_bytes_GBps": round(M.numel() * 4 / (ms_frame * 1e-3) / 1e9, 1)}
+    del M, vis, bvh
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_backward(prt, torch, scenegen, np, steps):
