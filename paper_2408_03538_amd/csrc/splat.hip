@@ -25,6 +25,7 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kTStop = 1e-4f;
 constexpr float kDilate = 0.3f;   // low-pass added to the 2D covariance (pixels^2)
 constexpr int kSub = 8;           // a wave's share of a tile: an 8 x 8-pixel quarter
+constexpr int kUnroll = 4;        // Gaussians evaluated together in the blend loop
 
 // Smallest value of q(x, y) = A dx^2 + 2 B dx dy + C dy^2 (dx = x - u, dy = y - v)
 // over the rectangle [x0, x1] x [y0, y1]: 0 with the centre inside, else the
@@ -243,28 +244,41 @@ __global__ __launch_bounds__(kTilePixels) void splat_render_kernel(SplatCamera c
         }
         __syncthreads();
         const int nb = (int)min((uint32_t)kTilePixels, rg.y - base);
-        for (int j = 0; j < nb; ++j) {
-            const float4 col = s_col[j];
-            if (!((__float_as_uint(col.w) >> wave) & 1u)) continue;   // uniform across the wave
+        // four Gaussians at a time: their alphas are independent, so they are
+        // evaluated together, then blended one after another in list order
+        for (int j0 = 0; j0 < nb; j0 += kUnroll) {
+            unsigned hit4 = 0;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (j0 + u < nb) hit4 |= ((__float_as_uint(s_col[j0 + u].w) >> wave) & 1u) << u;
+            if (hit4 == 0) continue;                      // uniform across the wave
             if (__all(done)) break;
-            if (done) continue;
-            const float2 c = s_uv[j];
-            const float4 co = s_co[j];
-            const float dx = c.x - fx, dy = c.y - fy;
-            const float power = -0.5f * (co.x * dx * dx + co.z * dy * dy) - co.y * dx * dy;
-            if (power > 0.0f) continue;
-            const float alpha = fminf(kAlphaMax, co.w * expf(power));
-            if (alpha < kAlphaMin) continue;
-            const float Tn = T * (1.0f - alpha);
-            if (Tn < kTStop) {
-                done = true;
-                continue;
+            float al[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int j = min(j0 + u, nb - 1);
+                const float2 c = s_uv[j];
+                const float4 co = s_co[j];
+                const float dx = c.x - fx, dy = c.y - fy;
+                const float power = -0.5f * (co.x * dx * dx + co.z * dy * dy) - co.y * dx * dy;
+                const float alpha = fminf(kAlphaMax, co.w * expf(power));
+                al[u] = ((hit4 >> u) & 1u) && power <= 0.0f && alpha >= kAlphaMin ? alpha : 0.0f;
             }
-            const float w = alpha * T;
-            C0 = fmaf(col.x, w, C0);
-            C1 = fmaf(col.y, w, C1);
-            C2 = fmaf(col.z, w, C2);
-            T = Tn;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (done || al[u] == 0.0f) continue;
+                const float Tn = T * (1.0f - al[u]);
+                if (Tn < kTStop) {
+                    done = true;
+                    continue;
+                }
+                const float4 col = s_col[j0 + u];
+                const float w = al[u] * T;
+                C0 = fmaf(col.x, w, C0);
+                C1 = fmaf(col.y, w, C1);
+                C2 = fmaf(col.z, w, C2);
+                T = Tn;
+            }
         }
         __syncthreads();
     }
