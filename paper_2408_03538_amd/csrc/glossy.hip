@@ -27,9 +27,11 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGlossyWaves = 4;
+constexpr int kPB = 2;            // 16-direction output blocks per pass over the input directions
+constexpr int kPad = 16 * kPB;    // the hemisphere list is padded to a multiple of this
 constexpr float kPi = 3.14159265358979323846f;
 
-// A wave's LDS: the hemisphere list for up to S + 16 entries (direction w
+// A wave's LDS: the hemisphere list for up to S + kPad entries (direction w
 // and c = n . w; n x w and V G1(c); table row), the two U blocks in transit,
 // and t, h.
 struct GlossyLds {
@@ -42,13 +44,13 @@ struct GlossyLds {
 
 __host__ __device__ inline size_t glossy_lds_bytes_per_wave(int S)
 {
-    const size_t e = (size_t)S + 16;
+    const size_t e = (size_t)S + kPad;
     return e * 36 + 2 * 16 * 17 * 4 + 2 * 16 * 4;
 }
 
 __device__ inline GlossyLds glossy_lds(char* base, int S)
 {
-    const size_t e = (size_t)S + 16;
+    const size_t e = (size_t)S + kPad;
     GlossyLds L;
     L.dir = reinterpret_cast<float4*>(base);
     L.crs = reinterpret_cast<float4*>(base + e * 16);
@@ -132,8 +134,8 @@ __global__ __launch_bounds__(64 * kGlossyWaves) void glossy_kernel(int n, int S,
         }
         H += __popcll(ball);
     }
-    // pad to a whole number of 16-entry blocks with finite, weightless entries
-    const int Hp = (H + 15) & ~15;
+    // pad to a whole number of kPad-entry blocks with finite, weightless entries
+    const int Hp = (H + kPad - 1) & ~(kPad - 1);
     if (H + lane < Hp) {
         L.dir[H + lane] = make_float4(nx, ny, nz, 1.0f);
         L.crs[H + lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -153,12 +155,20 @@ __global__ __launch_bounds__(64 * kGlossyWaves) void glossy_kernel(int n, int S,
 
     const int col = lane & 15, quad = lane >> 4;
     f32x4 mA = {0.0f, 0.0f, 0.0f, 0.0f}, mB = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int p0 = 0; p0 < Hp; p0 += 16) {
-        // this lane's output direction (B-operand column)
-        const float4 wp = L.dir[p0 + col];
-        const float4 cp = L.crs[p0 + col];
-        const float qp = (p0 + col < H) ? 0.25f / (wp.w * omk + k) : 0.0f;
-        f32x4 uA = {0.0f, 0.0f, 0.0f, 0.0f}, uB = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int p0 = 0; p0 < Hp; p0 += kPad) {
+        // this lane's output directions (B-operand column) in the pass's blocks
+        float4 wp[kPB], cp[kPB];
+        float qp[kPB];
+        f32x4 uA[kPB], uB[kPB];
+#pragma unroll
+        for (int b = 0; b < kPB; ++b) {
+            const int pj = p0 + 16 * b + col;
+            wp[b] = L.dir[pj];
+            cp[b] = L.crs[pj];
+            qp[b] = pj < H ? 0.25f / (wp[b].w * omk + k) : 0.0f;
+            uA[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            uB[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
         for (int s0 = 0; s0 < Hp; s0 += 4) {
             const int js = s0 + quad;                     // this lane's input direction (B-operand row)
             const float4 ws = L.dir[js];
@@ -166,41 +176,47 @@ __global__ __launch_bounds__(64 * kGlossyWaves) void glossy_kernel(int n, int S,
             const int row = L.idx[js];
             // A operand: Y_a(s) with a = col
             const float ya = col < K ? Y[(size_t)row * K + col] : 0.0f;
-            // BRDF for (s, p) with the unnormalised half vector v = ws + wp:
-            // D = alpha^2 / (pi x^2), x |v|^2 = |n x v|^2 + (n . v)^2 alpha^2
-            // (no cancellation as n . h -> 1), and wo . h = |v| / 2
-            const float hx = ws.x + wp.x, hy = ws.y + wp.y, hz = ws.z + wp.z;
-            const float hl2 = fmaxf(hx * hx + hy * hy + hz * hz, 1e-30f);
-            const float qx = cs.x + cp.x, qy = cs.y + cp.y, qz = cs.z + cp.z;
-            const float nv = ws.w + wp.w;
-            const float xh = fmaf(nv * nv, a2, qx * qx + qy * qy + qz * qz);
-            const float voh = fminf(0.5f * hl2 * __builtin_amdgcn_rsqf(hl2), 1.0f);
-            const float e = cs.w * a2_pi * (hl2 * hl2) * __builtin_amdgcn_rcpf(xh * xh);
-            const float t1 = 1.0f - voh, t2 = t1 * t1;
-            const float eB = e * (t2 * t2 * t1);
-            const float eA = e - eB;
-            uA = __builtin_amdgcn_mfma_f32_16x16x4f32(ya, eA, uA, 0, 0, 0);
-            uB = __builtin_amdgcn_mfma_f32_16x16x4f32(ya, eB, uB, 0, 0, 0);
-        }
-        // U[a][p] (a = 4 quad + j, p = col): scale by the output side's q_p and
-        // pass through LDS as the A operand of the contraction over p
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            L.u[0][4 * quad + j][col] = uA[j] * qp;
-            L.u[1][4 * quad + j][col] = uB[j] * qp;
+            for (int b = 0; b < kPB; ++b) {
+                // BRDF for (s, p) with the unnormalised half vector v = ws + wp:
+                // D = alpha^2 / (pi x^2), x |v|^2 = |n x v|^2 + (n . v)^2 alpha^2
+                // (no cancellation as n . h -> 1), and wo . h = |v| / 2
+                const float hx = ws.x + wp[b].x, hy = ws.y + wp[b].y, hz = ws.z + wp[b].z;
+                const float hl2 = fmaxf(hx * hx + hy * hy + hz * hz, 1e-30f);
+                const float qx = cs.x + cp[b].x, qy = cs.y + cp[b].y, qz = cs.z + cp[b].z;
+                const float nv = ws.w + wp[b].w;
+                const float xh = fmaf(nv * nv, a2, qx * qx + qy * qy + qz * qz);
+                const float voh = fminf(0.5f * hl2 * __builtin_amdgcn_rsqf(hl2), 1.0f);
+                const float e = cs.w * a2_pi * (hl2 * hl2) * __builtin_amdgcn_rcpf(xh * xh);
+                const float t1 = 1.0f - voh, t2 = t1 * t1;
+                const float eB = e * (t2 * t2 * t1);
+                const float eA = e - eB;
+                uA[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya, eA, uA[b], 0, 0, 0);
+                uB[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya, eB, uB[b], 0, 0, 0);
+            }
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            const int pl = 4 * kk + quad;                 // local output direction of this k slot
-            const int rowp = L.idx[p0 + pl];
-            const float yb = col < K ? Y[(size_t)rowp * K + col] : 0.0f;
-            mA = __builtin_amdgcn_mfma_f32_16x16x4f32(L.u[0][col][pl], yb, mA, 0, 0, 0);
-            mB = __builtin_amdgcn_mfma_f32_16x16x4f32(L.u[1][col][pl], yb, mB, 0, 0, 0);
+        for (int b = 0; b < kPB; ++b) {
+            // U[a][p] (a = 4 quad + j, p = col): scale by the output side's q_p and
+            // pass through LDS as the A operand of the contraction over p
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                L.u[0][4 * quad + j][col] = uA[b][j] * qp[b];
+                L.u[1][4 * quad + j][col] = uB[b][j] * qp[b];
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int pl = 4 * kk + quad;             // local output direction of this k slot
+                const int rowp = L.idx[p0 + 16 * b + pl];
+                const float yb = col < K ? Y[(size_t)rowp * K + col] : 0.0f;
+                mA = __builtin_amdgcn_mfma_f32_16x16x4f32(L.u[0][col][pl], yb, mA, 0, 0, 0);
+                mB = __builtin_amdgcn_mfma_f32_16x16x4f32(L.u[1][col][pl], yb, mB, 0, 0, 0);
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
     // t'_c[a][b] = wq^2 (F0_c A + B) + (1 - m) rho_c / pi t_a h_b, lane holds a = 4 quad + j, b = col
     const float w2 = wq * wq;
