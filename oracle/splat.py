@@ -148,7 +148,10 @@ def render(scene, colours, view, fx, fy, cx, cy, width, height, near_z, backgrou
         Tn = T * (1.0 - alpha)
         if want_allow:
             q = np.maximum(-2.0 * power, 0.0)
-            e = 0.5 * (24 * EPS32 * err["kappa"][g] * q + 2 * np.sqrt(q / err["lmin"][g]) * err["duv"][g]) + 4 * EPS32
+            # the exponential itself: an FP32 exp may go through 2^(x log2 e),
+            # whose rounded product adds about |x| log2(e) eps (|x| = q / 2)
+            e = 0.5 * (24 * EPS32 * err["kappa"][g] * q + 2 * np.sqrt(q / err["lmin"][g]) * err["duv"][g]) \
+                + (4 + q) * EPS32
             if not 24 * EPS32 * err["kappa"][g] < 0.5:
                 e = np.full(npix, np.inf)
             near_alpha = live & (np.abs(alpha - ALPHA_MIN) <= 4 * e * alpha)
