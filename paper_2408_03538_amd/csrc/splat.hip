@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kTilePixels) void splat_render_kernel(SplatCamera c
                 const float4 co = s_co[j];
                 const float dx = c.x - fx, dy = c.y - fy;
                 const float power = -0.5f * (co.x * dx * dx + co.z * dy * dy) - co.y * dx * dy;
-                const float alpha = fminf(kAlphaMax, co.w * expf(power));
+                const float alpha = fminf(kAlphaMax, co.w * __expf(power));
                 al[u] = ((hit4 >> u) & 1u) && power <= 0.0f && alpha >= kAlphaMin ? alpha : 0.0f;
             }
 #pragma unroll
