@@ -26,7 +26,7 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGlossyWaves = 4;
+constexpr int kGlossyWaves = 4;   // waves per block, fewer when their LDS would pass 64 KB
 constexpr int kPB = 2;            // 16-direction output blocks per pass over the input directions
 constexpr int kPad = 16 * kPB;    // the hemisphere list is padded to a multiple of this
 constexpr float kPi = 3.14159265358979323846f;
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(64 * kGlossyWaves) void glossy_kernel(int n, int S,
 {
     extern __shared__ __align__(16) char glossy_smem[];
     const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
-    const int i = blockIdx.x * kGlossyWaves + wave;
+    const int i = blockIdx.x * ((int)blockDim.x >> 6) + wave;
     if (i >= n) return;                  // whole waves only: each wave has its own LDS, no block barrier
     const GlossyLds L = glossy_lds(glossy_smem + (size_t)wave * glossy_lds_bytes_per_wave(S), S);
 
@@ -270,8 +270,11 @@ hipError_t launch_glossy(int n, int S, int K, const float* dirs, const float* Y,
                          float* out, unsigned* flags, hipStream_t stream)
 {
     if (n == 0) return hipSuccess;
-    const dim3 grid((n + kGlossyWaves - 1) / kGlossyWaves), block(64 * kGlossyWaves);
-    const size_t lds = kGlossyWaves * glossy_lds_bytes_per_wave(S);
+    const size_t per_wave = glossy_lds_bytes_per_wave(S);
+    int waves = kGlossyWaves;
+    while (waves > 1 && (size_t)waves * per_wave > 65536) --waves;
+    const dim3 grid((n + waves - 1) / waves), block(64 * waves);
+    const size_t lds = (size_t)waves * per_wave;
     if (K == 16)
         hipLaunchKernelGGL(glossy_kernel<16>, grid, block, lds, stream, n, S, dirs, Y, normals, albedo, roughness,
                            metallic, vis, out, flags);
