@@ -176,3 +176,13 @@ def test_splat_render_validation(lib):
     assert lib.prtgs_splat_workspace_bytes(0, 64, 48, 100) == 0
     assert lib.prtgs_splat_workspace_bytes(10, 0, 48, 100) == 0
     assert lib.prtgs_splat_workspace_bytes(10, 64, 48, 1 << 32) == 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 exits with a message before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
