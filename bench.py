@@ -122,7 +122,7 @@ def copy_only(mib):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this library has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_mib:
