@@ -25,7 +25,7 @@ constexpr float kAlphaMax = 0.99f;
 constexpr float kTStop = 1e-4f;
 constexpr float kDilate = 0.3f;   // low-pass added to the 2D covariance (pixels^2)
 constexpr int kSub = 8;           // a wave's share of a tile: an 8 x 8-pixel quarter
-constexpr int kUnroll = 4;        // Gaussians evaluated together in the blend loop
+constexpr int kUnroll = 8;        // Gaussians evaluated together in the blend loop
 
 // Smallest value of q(x, y) = A dx^2 + 2 B dx dy + C dy^2 (dx = x - u, dy = y - v)
 // over the rectangle [x0, x1] x [y0, y1]: 0 with the centre inside, else the
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kTilePixels) void splat_render_kernel(SplatCamera c
         }
         __syncthreads();
         const int nb = (int)min((uint32_t)kTilePixels, rg.y - base);
-        // four Gaussians at a time: their alphas are independent, so they are
+        // kUnroll Gaussians at a time: their alphas are independent, so they are
         // evaluated together, then blended one after another in list order
         for (int j0 = 0; j0 < nb; j0 += kUnroll) {
             unsigned hit4 = 0;
