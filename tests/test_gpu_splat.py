@@ -158,3 +158,16 @@ def test_splat_1080p_million_sampled(prt):
     assert np.median(r["allow_C"][covered]) < 5e-3
     print(f"1080p: {r['instances']} instances, covered {covered.mean():.2f}, |dC| max {r['dC'].max():.2e}, "
           f"median on covered {np.median(r['dC'][covered]):.2e}")
+
+
+def test_splat_general_intrinsics(prt):
+    """fx != fy and an off-centre principal point (the Jacobian clamp then
+    differs per side), with a rotated, translated camera."""
+    scene = _small_scene(82)
+    n = scene["means"].shape[0]
+    colours = np.random.default_rng(83).uniform(0, 1, (n, 3))
+    cam = prt.camera(prt.look_at((1.5, -3.0, 2.2), (-0.2, 0.3, 0.5), up=(0.1, 0.0, 1.0)), 112, 72, 55.0, 0.05,
+                     (0.05, 0.0, 0.1))
+    cam.fx, cam.fy, cam.cx, cam.cy = 95.0, 70.0, 40.0, 45.5
+    r = _compare(prt, scene, colours, cam)
+    assert (r["T"] < 0.5).mean() > 0.1
