@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "libprtgs.so")
 
 PRTGS_OK = 0
 STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "unsupported", 4: "HIP error"}
+ERR_WORKSPACE_TOO_SMALL = 2
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 FLAG_NONFINITE = 0x1
 FLAG_STACK_OVERFLOW = 0x2

@@ -340,25 +340,35 @@ def splat_render(scene: Scene, colours: torch.Tensor, cam, max_instances: int | 
                  workspace: Workspace | None = None, want_T: bool = False, check: bool = False):
     """Render per-splat colours ([n, 3], or a [n, B, 3] relight output with
     `colours[:, b]`) with Gaussian splatting.  Returns (image [H, W, 3],
-    final transmittance [H, W] or None, number of (Gaussian, tile) pairs)."""
+    final transmittance [H, W] or None, number of (Gaussian, tile) pairs).
+    With max_instances left at None the workspace starts at 64 pairs per
+    Gaussian and grows to the reported count if a frame needs more."""
     lib = _lib.load()
     n = scene.n
     if colours.dim() != 2 or colours.shape[0] != n or colours.shape[1] != 3 or colours.dtype != F32:
         raise ValueError("colours must be float32 [n, 3] (rows may be strided)")
     if colours.stride(1) != 1:
         raise ValueError("colour rows must be contiguous")
-    if max_instances is None:
+    grow = max_instances is None
+    if grow:
         max_instances = min(64 * n, 2**32 - 1)
     g = scene.c_struct()
-    wbytes = lib.prtgs_splat_workspace_bytes(n, cam.width, cam.height, max_instances)
-    if wbytes == 0:
-        raise _lib.PrtgsError(1, "invalid splat parameters")
-    ws = (workspace or Workspace()).get(wbytes, scene.device)
     image = torch.empty((cam.height, cam.width, 3), dtype=F32, device=scene.device)
     T = torch.empty((cam.height, cam.width), dtype=F32, device=scene.device) if want_T else None
-    inst = ctypes.c_int64(0)
-    _lib.check(lib.prtgs_splat_render(ctypes.byref(g), _ptr(colours), colours.stride(0), ctypes.byref(cam), _ptr(image),
-                                      _ptr(T), max_instances, _ptr(ws), ws.numel(), ctypes.byref(inst), _stream()))
+    workspace = workspace or Workspace()
+    while True:
+        wbytes = lib.prtgs_splat_workspace_bytes(n, cam.width, cam.height, max_instances)
+        if wbytes == 0:
+            raise _lib.PrtgsError(1, "invalid splat parameters")
+        ws = workspace.get(wbytes, scene.device)
+        inst = ctypes.c_int64(0)
+        st = lib.prtgs_splat_render(ctypes.byref(g), _ptr(colours), colours.stride(0), ctypes.byref(cam), _ptr(image),
+                                    _ptr(T), max_instances, _ptr(ws), ws.numel(), ctypes.byref(inst), _stream())
+        if grow and st == _lib.ERR_WORKSPACE_TOO_SMALL and max_instances < inst.value <= 2**32 - 1:
+            max_instances = int(inst.value)
+            continue
+        _lib.check(st)
+        break
     if check:
         check_flags(ws, "splat_render")
     return image, T, int(inst.value)

@@ -171,3 +171,18 @@ def test_splat_general_intrinsics(prt):
     cam.fx, cam.fy, cam.cx, cam.cy = 95.0, 70.0, 40.0, 45.5
     r = _compare(prt, scene, colours, cam)
     assert (r["T"] < 0.5).mean() > 0.1
+
+
+def test_splat_workspace_grows_when_defaulted(prt):
+    """A few Gaussians that each cover the whole frame need more than 64 pairs
+    per Gaussian: the default workspace grows to the reported count."""
+    n = 12
+    rng = np.random.default_rng(84)
+    scene = as_f32(dict(means=np.column_stack([rng.uniform(-0.2, 0.2, (n, 2)), rng.uniform(1.5, 3.0, n)]),
+                        quats=np.tile([1.0, 0.0, 0.0, 0.0], (n, 1)), log_scales=np.log(np.full((n, 3), 1.5)),
+                        opacity=rng.uniform(0.05, 0.3, n), normals=np.tile([0.0, 0.0, -1.0], (n, 1)),
+                        albedo=np.full((n, 3), 0.5)))
+    colours = rng.uniform(0, 1, (n, 3))
+    cam = prt.camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0], 256, 192, 60.0, 0.05)
+    r = _compare(prt, scene, colours, cam)
+    assert r["instances"] > 64 * n
