@@ -363,6 +363,22 @@ def bench_frame(prt, torch, np, sc, transfer, light, frames=20):
             "gaussian_tile_pairs": inst, "covered_pixel_frac_T_below_half": round(covered, 3)}
 
 
+def measured_copy_GBps(torch, mib=1024, reps=10):
+    """Read + write bandwidth of a plain 1 GiB device copy, for scale."""
+    x = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    return round(2 * mib * (1 << 20) / (ms * 1e-3) / 1e9, 1)
+
+
 def bench_relight(prt, torch, scenegen, np, steps):
     """3,000,000 RGB transfers x 64 lights: FP32, BF16 and F16 storage."""
     import oracle
@@ -407,10 +423,17 @@ def bench_relight(prt, torch, scenegen, np, steps):
                      "hbm_GBps": round((in_bytes + out_bytes) / (ms * 1e-3) / 1e9, 1),
                      "hbm_frac": round((in_bytes + out_bytes) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                      "max_rel_err": float((err / scale).max()), "mean_rel_err": float((err / scale).mean())}
+        # the dot products themselves (2 K flops per splat, light and channel)
+        # against the dense peak of the unit that runs them
+        flops = n * B * 3 * 2 * T.shape[2]
+        peak = PEAK_FP32_TFLOPS if odt == "f32" and t.dtype == torch.float32 else PEAK_BF16_TFLOPS
+        res[name]["algorithmic_TFLOPs"] = round(flops / (ms * 1e-3) / 1e12, 2)
+        res[name]["compute_frac"] = round(flops / (ms * 1e-3) / 1e12 / peak, 4)
         log(f"relight {name}: {ms:.3f} ms, {res[name]['hbm_GBps']} GB/s, max err {res[name]['max_rel_err']:.2e}")
     res["speedup_bf16_f16out_vs_f32"] = round(res["f32->f32"]["ms"] / res["bf16->f16"]["ms"], 3)
     res["speedup_bf16_f32out_vs_f32"] = round(res["f32->f32"]["ms"] / res["bf16->f32"]["ms"], 3)
     res["workload"] = "3,000,000 splats x 16 coeffs x RGB, 64 light environments"
+    res["copy_GBps"] = measured_copy_GBps(torch)
     del T, T16, out32, out16
     torch.cuda.empty_cache()
     return res
