@@ -186,3 +186,34 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_glossy_validation(lib):
+    from paper_2408_03538_amd import _lib
+    g = _gaussians()
+    g.albedo = 256
+    d = lambda S=64, bands=4: _lib.TransferDesc(S, bands, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0)
+    assert lib.prtgs_glossy_workspace_bytes(ctypes.byref(d())) > 64 * 4 * 19
+    assert lib.prtgs_glossy_workspace_bytes(ctypes.byref(d(S=513))) == 0      # more than 512 directions
+    assert lib.prtgs_glossy_workspace_bytes(ctypes.byref(d(bands=2))) == 0    # 3 or 4 bands only
+    call = lambda g=g, desc=d(), rough=256, vis=256, out=256, ws=256: lib.prtgs_glossy_transfer(
+        ctypes.byref(g), rough, 256, ctypes.byref(desc), vis, out, ws, 1 << 20, None)
+    no_albedo = _gaussians()
+    assert call(g=no_albedo) == 1
+    assert call(desc=d(S=600)) == 1
+    assert call(desc=d(bands=5)) == 1
+    assert call(rough=None) == 1
+    assert call(vis=None) == 1
+    assert call(out=None) == 1
+    assert call(ws=256 + 4) == 1                    # workspace not 256-byte aligned
+    assert lib.prtgs_glossy_transfer(ctypes.byref(g), 256, 256, ctypes.byref(d()), 256, 256, 256, 16, None) == 2
+
+
+def test_glossy_view_validation(lib):
+    eye = (ctypes.c_float * 3)(0.0, 0.0, 5.0)
+    bad = (ctypes.c_float * 3)(0.0, float("nan"), 5.0)
+    assert lib.prtgs_glossy_view(10, 5, 256, 256, eye, 256, None) == 1          # K must be 9 or 16
+    assert lib.prtgs_glossy_view(10, 16, 256, 256, bad, 256, None) == 1         # eye not finite
+    assert lib.prtgs_glossy_view(10, 16, None, 256, eye, 256, None) == 1
+    assert lib.prtgs_glossy_view(-1, 16, 256, 256, eye, 256, None) == 1
+    assert lib.prtgs_glossy_view(0, 16, None, None, eye, None, None) == 0       # nothing to do
