@@ -311,9 +311,34 @@ def bench_million(prt, torch, scenegen, np):
     log(f"million index mode: direct + index + 3 bounces {t_all:.0f} ms, one gather bounce {t_gather:.2f} ms")
     del out3, ws3, idx, prev
     out_d["frame_1080p"] = bench_frame(prt, torch, np, sc, res["transfer_out"], light)
-    del res, out
+    del out
+    torch.cuda.empty_cache()
+    out_d["glossy_1m"] = bench_glossy_million(prt, torch, scenegen, np, sc, res["bvh"], params)
+    del res
     torch.cuda.empty_cache()
     return out_d
+
+
+def bench_glossy_million(prt, torch, scenegen, np, sc, bvh, params):
+    """Glossy matrices of the million-splat scene at S = 512 from its direct
+    pass's visibilities (materials U[0.1, 1] x U[0, 1])."""
+    rough, metal = scenegen.materials(sc.n, scenegen.SEED_SCENE + 6)
+    r = torch.tensor(rough, dtype=torch.float32, device="cuda")
+    m = torch.tensor(metal, dtype=torch.float32, device="cuda")
+    pd = prt.TransferParams(num_dirs=params.num_dirs, sh_bands=params.sh_bands)
+    _, vis = prt.precompute_transfer(sc, bvh, pd, want_vis=True)
+    ws = prt.Workspace()
+    M = prt.glossy_transfer(sc, pd, vis, r, m, workspace=ws)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    prt.glossy_transfer(sc, pd, vis, r, m, out=M, workspace=ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    log(f"glossy 1M x 512: {ms:.1f} ms")
+    del M, vis
+    return {"workload": "million-splat scene, S=512, 3 x 16 x 16 matrices, roughness U[0.1,1], metallic U[0,1]",
+            "ms_glossy_matrices": round(ms, 2), "matrices_per_s": round(sc.n / (ms * 1e-3), 1)}
 
 
 def frame_only(prt, torch, scenegen, np):
