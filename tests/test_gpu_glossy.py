@@ -133,3 +133,19 @@ def test_glossy_surface100k_sampled(prt, oracle_mod):
     err = np.abs(got[src] - ref["t"])
     assert (err <= ref["allow"] + 1e-9).all()
     print(f"glossy100k: max |d| {err.max():.2e}")
+
+
+def test_glossy_million_sampled(prt, oracle_mod):
+    """The million-splat scene at S = 512 (the configuration the benchmark
+    times): 6 sampled splats end to end against the oracle."""
+    from oracle import glossy
+    scene = as_f32(scenegen.million_scene(scenegen.SEED_SCENE + 2))
+    n = scene["means"].shape[0]
+    rough, metal = (np.asarray(v, np.float32).astype(np.float64)
+                    for v in scenegen.materials(n, scenegen.SEED_SCENE + 6))
+    got = _gpu_matrices(prt, scene, rough, metal, 512, 4)
+    src = np.random.default_rng(98).choice(n, 6, replace=False)
+    ref = glossy.glossy_transfer(scene, 512, 4, rough, metal, sources=src, want_allow=True)
+    err = np.abs(got[src] - ref["t"])
+    assert (err <= ref["allow"] + 1e-9).all()
+    print(f"glossy 1M x 512: max |d| {err.max():.2e}")
