@@ -14,6 +14,7 @@ baseline.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
     python bench.py --copy-mib M      # plain device copy (counter calibration)
     python bench.py --frame-only      # relit 1080p frames of the million-splat scene
+    python bench.py --relight-only    # the 3M x 64 relight alone
 """
 from __future__ import annotations
 
@@ -73,6 +74,8 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=0, help="only run a plain device copy of this size")
     ap.add_argument("--frame-only", action="store_true",
                     help="only time relit 1080p frames of the million-splat scene (synthetic transfers)")
+    ap.add_argument("--relight-only", action="store_true",
+                    help="only time the 3M x 64 relight in FP32, BF16 and F16 storage")
     return ap.parse_args()
 
 
@@ -138,6 +141,9 @@ def main():
     torch.cuda.set_device(0)
     if args.frame_only:
         frame_only(prt, torch, scenegen, np)
+        return
+    if args.relight_only:
+        print(json.dumps({"relight_3m": bench_relight(prt, torch, scenegen, np, args.steps)}), flush=True)
         return
     log("generating the 100k surface workload")
     arr, sc, params, light = workload_setup(prt, torch, scenegen, "surface100k")
