@@ -190,3 +190,19 @@ def test_visibility_enters_linearly():
     half = glossy.glossy_transfer(sc, S, bands, rough, metal, sources=[1, 2], vis=0.5 * vis)
     assert np.allclose(half, 0.5 * traced, rtol=1e-12, atol=1e-15)
     assert (glossy.glossy_transfer(sc, S, bands, rough, metal, sources=[1], vis=np.zeros((1, S))) == 0).all()
+
+
+def test_view_transfer_contracts_the_output_index():
+    """z[c][a] = sum_b t'[c][a][b] Y_b(wo): a unit matrix entry (a = 2, b = 5)
+    gives Y_5(wo) in slot a = 2 and zeros elsewhere; a light l then sees
+    l_2 Y_5(wo), the outgoing radiance of Eq. 41 for that entry."""
+    wo = _unit([[0.3, -0.5, 0.8]])
+    y = oracle.sh_basis(4, wo)                      # [1, 16]
+    t = np.zeros((1, 3, 16, 16))
+    t[0, 1, 2, 5] = 1.0
+    z = glossy.view_transfer(t, y)
+    expect = np.zeros((1, 3, 16))
+    expect[0, 1, 2] = y[0, 5]
+    assert np.array_equal(z, expect)
+    # Y_5 is the (l = 2, m = -1) function: -sqrt(15 / (4 pi)) y z for a unit vector
+    assert math.isclose(y[0, 5], -math.sqrt(15 / (4 * math.pi)) * wo[0, 1] * wo[0, 2], rel_tol=1e-12)
