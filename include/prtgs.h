@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PRTGS_ABI_VERSION 2
+#define PRTGS_ABI_VERSION 3   /* 3: splatting and glossy entry points */
 
 typedef enum {
     PRTGS_OK = 0,

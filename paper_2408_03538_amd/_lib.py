@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libprtgs.so")
 
 PRTGS_OK = 0
+ABI_VERSION = 3   # PRTGS_ABI_VERSION of include/prtgs.h that these declarations follow
 STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "unsupported", 4: "HIP error"}
 ERR_WORKSPACE_TOO_SMALL = 2
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
@@ -101,6 +102,9 @@ def load():
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args
+        if lib.prtgs_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI {lib.prtgs_abi_version()}, these bindings expect {ABI_VERSION}: "
+                               "rebuild it with `python -m paper_2408_03538_amd.build`")
         _handle = lib
     return _handle
 

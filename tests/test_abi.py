@@ -37,7 +37,7 @@ def test_binding_covers_the_header():
 
 
 def test_abi_version(lib):
-    assert lib.prtgs_abi_version() == 2
+    assert lib.prtgs_abi_version() == 3
 
 
 def test_size_queries(lib):
