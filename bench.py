@@ -45,7 +45,7 @@ FLOPS_PER_PRIM_TEST = 70
 # counter runs (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy): see
 # profiles/direct_kernel_surface100k_hbm_counters.md.  Valid only for the
 # kernel sources it was measured on (hash below); null otherwise.
-MEASURED_TRAFFIC = {"sources_sha256_16": "fd8d789ca0b5e920", "bytes_per_launch": 7.817e9}
+MEASURED_TRAFFIC = {"sources_sha256_16": "57c90150be1eeeca", "bytes_per_launch": 7.821e9}
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
                   "paper_2408_03538_amd/csrc/common.hpp"]
 

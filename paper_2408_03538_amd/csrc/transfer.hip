@@ -515,7 +515,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                             k_last = bk[q];
                             started = true;
                             ++got;
-                            if (T < hp.T_eps) done = true;
+                            // no later hit can outweigh the best one: its W_j <= T_j <= T
+                            // (each FP32 product by a factor <= 1 stays <= T)
+                            if (T < hp.T_eps || T <= bestW) done = true;
                         } else if (!kIndex && more && !done && bk[q] != kNoHit) {
                             const int r = key_j(bk[q]);
                             const float w = ba[q] * T * wc;
