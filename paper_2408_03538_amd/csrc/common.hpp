@@ -144,6 +144,8 @@ struct TransferArgs {
     float4* albedo_sorted;  // [n] leaf order (bounce scratch), or null
     uint64_t* hitkey;       // bounce: per-lane hit lists of the persistent waves,
     float* hitalpha;        // [wave][kHitList][64] keys (t bits, leaf rank) and alphas
+    int2* hitrec;           // blend: [wave][kHitList][64] (leaf rank, weight) of the
+                            // hits blended in the current round, in blend order
     unsigned* queue;        // bounce: work counter (zeroed before the launch)
     float* tcut;            // [count][S] direction-order position: depth of the
                             // farthest hit the direct pass used before the ray

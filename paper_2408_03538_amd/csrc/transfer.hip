@@ -290,7 +290,10 @@ __device__ inline int key_j(uint64_t k) { return (int)(uint32_t)k; }
 // of the lane's own in device memory, unsorted (the traversal meets them in
 // no useful order).  Afterwards the lane blends the list nearest first,
 // kBlend hits at a time: one pass over the list (coalesced across the wave)
-// keeps the kBlend nearest unblended keys in a sorted register buffer.  A
+// keeps the kBlend nearest unblended keys in a sorted register buffer, and
+// each blended hit's weight goes to a per-lane record list; the records are
+// summed into the transfer once the round's selection is over, so that the
+// 3K sums are not live during the traversal or the scans.  A
 // list that fills up is compacted around the mean depth of its hits: those
 // beyond it are dropped and every later hit beyond it is refused (k_over), so
 // the list stays complete in front of k_over; the lane blends it and, if
@@ -306,7 +309,7 @@ constexpr int kCheck = 8;   // depth checkpoints per ray and round
 // hits with T_j <= t_same (the nearer one on equal weights) in the index
 // matrix (-1: none, or not traced), and nothing is accumulated.
 template <int K, bool kIndex>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void bounce_kernel(TransferArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void bounce_kernel(TransferArgs a)
 {
     constexpr int M = kHitList;
     const int lane = threadIdx.x & (kWave - 1);
@@ -315,6 +318,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     const int wslot = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     uint64_t* const lkey = a.hitkey + (size_t)wslot * M * kWave + lane;   // entry q at [q * kWave]
     float* const lalpha = a.hitalpha + (size_t)wslot * M * kWave + lane;
+    int2* const lrec = kIndex ? nullptr : a.hitrec + (size_t)wslot * M * kWave + lane;
     const int groups = (a.count + G - 1) / G;
     const HitParams hp = a.hp;
     // Each traversal blends at least one of at most n - 1 hits, hence the cap.
@@ -334,12 +338,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const float4 nrm = a.normals[rank];
         const int orig = valid ? a.order[rank] : 0;
         const float scale = kFourPi / (float)a.S;
-
-        float acc[3][K];
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch)
-#pragma unroll
-            for (int k = 0; k < K; ++k) acc[ch][k] = 0.0f;
 
         for (int b0 = 0; b0 < a.S; b0 += D) {
             const int pos = b0 + (lane % D);
@@ -453,6 +451,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 for (int off = 32; off >= 1; off >>= 1) maxcnt = max(maxcnt, __shfl_xor(maxcnt, off, kWave));
                 bool done = false;
                 bool more = pending && cnt > 0;   // listed hits left to blend
+                int nrec = 0;                     // hits blended this round (at most cnt)
                 while (__ballot(more) != 0ull) {
                     uint64_t bk[kBlend];
                     float ba[kBlend];
@@ -519,31 +518,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                             // (each FP32 product by a factor <= 1 stays <= T)
                             if (T < hp.T_eps || T <= bestW) done = true;
                         } else if (!kIndex && more && !done && bk[q] != kNoHit) {
-                            const int r = key_j(bk[q]);
-                            const float w = ba[q] * T * wc;
-                            const float4 rho = a.albedo_sorted[r];
-                            float tv[K];
-                            if constexpr (K % 4 == 0) {
-                                const float4* td = reinterpret_cast<const float4*>(a.tdir_sorted + (size_t)r * K);
-#pragma unroll
-                                for (int k4 = 0; k4 < K / 4; ++k4) {
-                                    const float4 v = td[k4];
-                                    tv[4 * k4] = v.x;
-                                    tv[4 * k4 + 1] = v.y;
-                                    tv[4 * k4 + 2] = v.z;
-                                    tv[4 * k4 + 3] = v.w;
-                                }
-                            } else {
-#pragma unroll
-                                for (int k = 0; k < K; ++k) tv[k] = a.tdir_sorted[(size_t)r * K + k];
-                            }
-                            const float r0 = rho.x * w, r1 = rho.y * w, r2 = rho.z * w;
-#pragma unroll
-                            for (int k = 0; k < K; ++k) {
-                                acc[0][k] = fmaf(r0, tv[k], acc[0][k]);
-                                acc[1][k] = fmaf(r1, tv[k], acc[1][k]);
-                                acc[2][k] = fmaf(r2, tv[k], acc[2][k]);
-                            }
+                            // the hit's weight, summed into the transfer after the selection
+                            lrec[nrec * kWave] = make_int2(key_j(bk[q]), __float_as_int(ba[q] * T * wc));
+                            ++nrec;
                             T *= 1.0f - ba[q];
                             k_last = bk[q];
                             started = true;
@@ -556,10 +533,44 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                 }
                 // a list that overflowed and is still transparent: traverse on
                 if (done || k_over == kNoHit) pending = false;
-                // Add this round to the source's transfer (the D lanes of a
-                // source summed first), so that the sums are dead during the
-                // next traversal.
+                // Sum the round's blended hits in blend order and add them to
+                // the source's transfer (the D lanes of a source summed
+                // first).  The sums live only here, not across the selection
+                // or the traversal, which keeps both free of spills.
                 if constexpr (!kIndex) {
+                    float acc[3][K];
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+                        for (int k = 0; k < K; ++k) acc[ch][k] = 0.0f;
+                    for (int q = 0; q < nrec; ++q) {
+                        const int2 e = lrec[q * kWave];
+                        const int r = e.x;
+                        const float w = __int_as_float(e.y);
+                        const float4 rho = a.albedo_sorted[r];
+                        float tv[K];
+                        if constexpr (K % 4 == 0) {
+                            const float4* td = reinterpret_cast<const float4*>(a.tdir_sorted + (size_t)r * K);
+#pragma unroll
+                            for (int k4 = 0; k4 < K / 4; ++k4) {
+                                const float4 v = td[k4];
+                                tv[4 * k4] = v.x;
+                                tv[4 * k4 + 1] = v.y;
+                                tv[4 * k4 + 2] = v.z;
+                                tv[4 * k4 + 3] = v.w;
+                            }
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < K; ++k) tv[k] = a.tdir_sorted[(size_t)r * K + k];
+                        }
+                        const float r0 = rho.x * w, r1 = rho.y * w, r2 = rho.z * w;
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            acc[0][k] = fmaf(r0, tv[k], acc[0][k]);
+                            acc[1][k] = fmaf(r1, tv[k], acc[1][k]);
+                            acc[2][k] = fmaf(r2, tv[k], acc[2][k]);
+                        }
+                    }
 #pragma unroll
                     for (int ch = 0; ch < 3; ++ch) {
                         float* out = a.transfer + ((size_t)orig * 3 + ch) * K;
@@ -567,7 +578,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                         for (int k = 0; k < K; ++k) {
                             const float v = segment_sum(acc[ch][k], D) * scale;
                             if (valid && (lane % D) == 0) out[k] += v;
-                            acc[ch][k] = 0.0f;
                         }
                     }
                 }
