@@ -77,7 +77,7 @@ prtgs_status check_desc(const prtgs_transfer_desc* d)
 }
 
 struct TransferWs {
-    size_t dirs, Y, dir_order, tdir, albedo, tcut, queue, hitkey, hitalpha, hitrec, index, term0, term1, total;
+    size_t dirs, Y, dir_order, rayw, tdir, albedo, tcut, queue, hitkey, hitalpha, hitrec, index, term0, term1, total;
 };
 
 TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
@@ -91,6 +91,8 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     off += align256(sizeof(float) * (size_t)K * (size_t)d.num_dirs);
     w.dir_order = off;
     off += align256(sizeof(int32_t) * (size_t)d.num_dirs);
+    w.rayw = off;
+    off += align256(sizeof(float) * (size_t)n * (size_t)d.num_dirs);
     w.tdir = off;
     if (d.bounces) off += align256(sizeof(float) * (size_t)K * (size_t)n);
     w.albedo = off;
@@ -242,6 +244,7 @@ TransferArgs transfer_args(const prtgs_gaussians* g, const void* bvh, const prtg
     a.tdir_sorted = bounce ? reinterpret_cast<float*>(w + W.tdir) : nullptr;
     a.albedo = g->albedo;
     a.albedo_sorted = bounce ? reinterpret_cast<float4*>(w + W.albedo) : nullptr;
+    a.rayw = reinterpret_cast<float*>(w + W.rayw);
     a.tcut = bounce ? reinterpret_cast<float*>(w + W.tcut) : nullptr;
     a.queue = bounce ? reinterpret_cast<unsigned*>(w + W.queue) : nullptr;
     a.hitkey = bounce ? reinterpret_cast<uint64_t*>(w + W.hitkey) : nullptr;

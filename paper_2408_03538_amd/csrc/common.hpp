@@ -147,6 +147,9 @@ struct TransferArgs {
     int2* hitrec;           // blend: [wave][kHitList][64] (leaf rank, weight) of the
                             // hits blended in the current round, in blend order
     unsigned* queue;        // bounce: work counter (zeroed before the launch)
+    float* rayw;            // [S][count] direction-order position: T c of each
+                            // ray of the direct pass (0 below the horizon),
+                            // summed against Y by the projection
     float* tcut;            // [count][S] direction-order position: depth of the
                             // farthest hit the direct pass used before the ray
                             // turned opaque (+inf if it never did), or null

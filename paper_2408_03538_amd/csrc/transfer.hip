@@ -8,10 +8,11 @@
 // stratum tiles, Morton order inside, so aligned runs stay in one octant and
 // a compact patch of the sphere); lane l traces source l / D along direction
 // l % D.  Neighbouring origins share the Gaussians around them, nearby
-// directions share the far field.  Each lane accumulates the SH projection
-// of its own rays (compensated sums); the D lanes of a source are added at
-// the end.  Small scenes use the "fan" split instead (one source per wave,
-// its hemisphere directions compacted over the lanes) to fill the GPU.
+// directions share the far field.  Each ray's weight T max(n . w, 0) is
+// stored, and a second kernel projects every source's S weights onto SH in
+// FP64, in direction order, so the transfer does not depend on the split.
+// Small scenes use the "fan" split instead (one source per wave, its
+// hemisphere directions compacted over the lanes) to fill the GPU.
 #include "trace.hpp"
 
 namespace prtgs {
@@ -21,14 +22,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr float kFourPi = 12.566370614359172f;
 constexpr float kInvPi = 0.31830988618379067f;
-
-__device__ inline void kahan_add(float& sum, float& comp, float x)
-{
-    float y = x - comp;
-    float t = sum + y;
-    comp = (t - sum) - y;
-    sum = t;
-}
 
 // Sum of v over each aligned run of D lanes (D a power of two).
 __device__ inline float segment_sum(float v, int D)
@@ -76,12 +69,17 @@ __device__ inline void traverse_batch(const TransferArgs& a, const RayDir& d, co
 
 // ---------------------------------------------------------------------------
 // direct transfer, group split
+// Each ray's T max(n . w, 0) goes to rayw and project_kernel forms the SH
+// sums: with no sums held across the traversal the kernel fits 64 VGPRs, 8
+// waves per SIMD, which hides more of the latency of its dependent record
+// loads than the 5 waves that the register-held sums allowed.
 // stats (kCount): [0] traced rays, [1] child-box tests, [2] Gaussian tests
 // (single-ray work, summed over rays), [3] wave node visits, [4] wave
 // Gaussian-record visits (summed over waves and batches).
 // ---------------------------------------------------------------------------
-template <int K, bool kCount>
-__global__ __launch_bounds__(kBlock) void direct_kernel(TransferArgs a, unsigned long long* stats)
+template <bool kCount>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void direct_kernel(TransferArgs a,
+                                                                                                unsigned long long* stats)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int G = a.G;
@@ -95,12 +93,6 @@ __global__ __launch_bounds__(kBlock) void direct_kernel(TransferArgs a, unsigned
     const float4 nrm = a.normals[rank];
     const int orig = valid ? a.order[rank] : 0;
     const HitParams hp = a.hp;
-    float acc[K], cmp[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        acc[k] = 0.0f;
-        cmp[k] = 0.0f;
-    }
     RayCounts cnt;
     uint32_t traced_rays = 0;
     for (int b0 = 0; b0 < a.S; b0 += D) {
@@ -111,6 +103,7 @@ __global__ __launch_bounds__(kBlock) void direct_kernel(TransferArgs a, unsigned
         const float c = nrm.x * d.wx + nrm.y * d.wy + nrm.z * d.wz;
         const bool traced = valid && inrange && c > 0.0f;
         if (!kCount && valid && inrange && !traced) {
+            a.rayw[(size_t)pos * a.count + local] = 0.0f;
             if (a.vis) a.vis[(size_t)orig * a.S + s] = -1.0f;
             if (a.tcut) a.tcut[(size_t)local * a.S + pos] = 0.0f;
         }
@@ -135,9 +128,7 @@ __global__ __launch_bounds__(kBlock) void direct_kernel(TransferArgs a, unsigned
         };
         traverse_batch<kCount>(a, d, bd, ox, oy, oz, live, tlo, thi, leaf, &cnt);
         if (!kCount && traced) {
-            const float f = T * c;
-#pragma unroll
-            for (int k = 0; k < K; ++k) kahan_add(acc[k], cmp[k], f * a.Y[(size_t)s * K + k]);
+            a.rayw[(size_t)pos * a.count + local] = T * c;
             if (a.vis) a.vis[(size_t)orig * a.S + s] = T;
             if (a.tcut) a.tcut[(size_t)local * a.S + pos] = T == 0.0f ? tfar : INFINITY;
         }
@@ -150,35 +141,68 @@ __global__ __launch_bounds__(kBlock) void direct_kernel(TransferArgs a, unsigned
             atomicAdd(&stats[3], (unsigned long long)cnt.wave_nodes);
             atomicAdd(&stats[4], (unsigned long long)cnt.wave_leaves);
         }
-        return;
     }
-    const float scale = kFourPi / (float)a.S;
+}
+
+// The SH projection of the direct pass (Eq. 29 over the S directions):
+// one thread per source sums rayw[pos] Y(w_s) over the direction-order
+// positions in FP64 (loads of 8 positions in flight; the direction's Y row is
+// uniform across the wave and comes through the scalar unit), then writes the
+// transfer (copied to every channel) and, for a bounce, the leaf-order copies.
+template <int K>
+__global__ __launch_bounds__(kBlock) void project_kernel(TransferArgs a)
+{
+    const int local = blockIdx.x * kBlock + threadIdx.x;
+    if (local >= a.count) return;
+    const int rank = a.first + local;
+    double acc[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = segment_sum(acc[k] - cmp[k], D) * scale;
-    if (valid && (lane % D) == 0) {
-        for (int ch = 0; ch < a.channels; ++ch) {
-            float* out = a.transfer + ((size_t)orig * a.channels + ch) * K;
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    constexpr int kAhead = 8;
+    int pos = 0;
+    for (; pos + kAhead <= a.S; pos += kAhead) {
+        float w[kAhead];
 #pragma unroll
-            for (int k = 0; k < K; ++k) out[k] = acc[k];
+        for (int u = 0; u < kAhead; ++u) w[u] = a.rayw[(size_t)(pos + u) * a.count + local];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            const float* y = a.Y + (size_t)a.dir_order[pos + u] * K;
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] = fma((double)w[u], (double)y[k], acc[k]);
         }
-        if (a.tdir_sorted) {
+    }
+    for (; pos < a.S; ++pos) {
+        const float w = a.rayw[(size_t)pos * a.count + local];
+        const float* y = a.Y + (size_t)a.dir_order[pos] * K;
 #pragma unroll
-            for (int k = 0; k < K; ++k) a.tdir_sorted[(size_t)rank * K + k] = acc[k];
-            const int j = orig;
-            a.albedo_sorted[rank] = make_float4(a.albedo[3 * (size_t)j], a.albedo[3 * (size_t)j + 1],
-                                                a.albedo[3 * (size_t)j + 2], 0.0f);
-        }
+        for (int k = 0; k < K; ++k) acc[k] = fma((double)w, (double)y[k], acc[k]);
+    }
+    const double scale = 4.0 * 3.14159265358979323846 / (double)a.S;
+    float t[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) t[k] = (float)(acc[k] * scale);
+    const int orig = a.order[rank];
+    for (int ch = 0; ch < a.channels; ++ch) {
+        float* out = a.transfer + ((size_t)orig * a.channels + ch) * K;
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] = t[k];
+    }
+    if (a.tdir_sorted) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) a.tdir_sorted[(size_t)rank * K + k] = t[k];
+        a.albedo_sorted[rank] = make_float4(a.albedo[3 * (size_t)orig], a.albedo[3 * (size_t)orig + 1],
+                                            a.albedo[3 * (size_t)orig + 2], 0.0f);
     }
 }
 
 // ---------------------------------------------------------------------------
 // direct transfer, fan split (small scenes): one wave per source; the
 // directions above its horizon are compacted (coherent order) into a
-// per-wave list in LDS and traced 64 at a time.
+// per-wave list in LDS and traced 64 at a time.  Rays go to rayw like those
+// of the group split, so both give the same transfer.
 // ---------------------------------------------------------------------------
 constexpr int kFanMaxDirs = 1024;   // per-wave direction list capacity (LDS)
 
-template <int K>
 __global__ __launch_bounds__(kBlock) void direct_fan_kernel(TransferArgs a)
 {
     __shared__ int16_t list[kBlock / kWave][kFanMaxDirs];
@@ -193,12 +217,6 @@ __global__ __launch_bounds__(kBlock) void direct_fan_kernel(TransferArgs a)
     const int orig = uniform_load(a.order, rank);
     const HitParams hp = a.hp;
     const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    float acc[K], cmp[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        acc[k] = 0.0f;
-        cmp[k] = 0.0f;
-    }
     for (int seg = 0; seg < a.S; seg += kFanMaxDirs) {
         const int seg_n = min(kFanMaxDirs, a.S - seg);
         int count = 0;
@@ -210,6 +228,7 @@ __global__ __launch_bounds__(kBlock) void direct_fan_kernel(TransferArgs a)
             const uint64_t m = __ballot(c > 0.0f);
             if (c > 0.0f) list[wslot][count + __popcll(m & lt_mask)] = (int16_t)pos;
             else if (pos < seg_n) {
+                a.rayw[(size_t)(seg + pos) * a.count + local] = 0.0f;
                 if (a.vis) a.vis[(size_t)orig * a.S + s] = -1.0f;
                 if (a.tcut) a.tcut[(size_t)local * a.S + seg + pos] = 0.0f;
             }
@@ -241,30 +260,12 @@ __global__ __launch_bounds__(kBlock) void direct_fan_kernel(TransferArgs a)
             };
             traverse_batch<false>(a, d, bd, ox, oy, oz, live, tlo, thi, leaf, (RayCounts*)nullptr);
             if (traced) {
-                const float f = T * c;
-#pragma unroll
-                for (int k = 0; k < K; ++k) kahan_add(acc[k], cmp[k], f * a.Y[(size_t)s * K + k]);
+                a.rayw[(size_t)(seg + list[wslot][idx]) * a.count + local] = T * c;
                 if (a.vis) a.vis[(size_t)orig * a.S + s] = T;
                 if (a.tcut) a.tcut[(size_t)local * a.S + seg + list[wslot][idx]] = T == 0.0f ? tfar : INFINITY;
             }
         }
         __builtin_amdgcn_wave_barrier();
-    }
-    const float scale = kFourPi / (float)a.S;
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = segment_sum(acc[k] - cmp[k], kWave) * scale;
-    if (lane == 0) {
-        for (int ch = 0; ch < a.channels; ++ch) {
-            float* out = a.transfer + ((size_t)orig * a.channels + ch) * K;
-#pragma unroll
-            for (int k = 0; k < K; ++k) out[k] = acc[k];
-        }
-        if (a.tdir_sorted) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) a.tdir_sorted[(size_t)rank * K + k] = acc[k];
-            a.albedo_sorted[rank] = make_float4(a.albedo[3 * (size_t)orig], a.albedo[3 * (size_t)orig + 1],
-                                                a.albedo[3 * (size_t)orig + 2], 0.0f);
-        }
     }
 }
 
@@ -657,14 +658,18 @@ template <int K>
 hipError_t launch_direct_k(const TransferArgs& a, unsigned long long* stats, hipStream_t stream)
 {
     if (stats) {
-        hipLaunchKernelGGL((direct_kernel<K, true>), dim3(group_blocks(a.count, a.G)), dim3(kBlock), 0, stream, a,
+        hipLaunchKernelGGL((direct_kernel<true>), dim3(group_blocks(a.count, a.G)), dim3(kBlock), 0, stream, a,
                            stats);
-    } else if (a.G == 1) {
-        hipLaunchKernelGGL(direct_fan_kernel<K>, dim3(group_blocks(a.count, 1)), dim3(kBlock), 0, stream, a);
-    } else {
-        hipLaunchKernelGGL((direct_kernel<K, false>), dim3(group_blocks(a.count, a.G)), dim3(kBlock), 0, stream, a,
-                           stats);
+        return hipGetLastError();
     }
+    if (a.G == 1)
+        hipLaunchKernelGGL(direct_fan_kernel, dim3(group_blocks(a.count, 1)), dim3(kBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL((direct_kernel<false>), dim3(group_blocks(a.count, a.G)), dim3(kBlock), 0, stream, a,
+                           stats);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(project_kernel<K>, dim3((a.count + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
