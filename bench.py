@@ -41,11 +41,12 @@ FLOPS_PER_BOX_TEST = 15
 FLOPS_PER_PRIM_TEST = 70
 
 
-# HBM traffic of the direct kernel on this workload, from two rocprofv3
-# counter runs (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy): see
-# profiles/direct_kernel_surface100k_hbm_counters.md.  Valid only for the
-# kernel sources it was measured on (hash below); null otherwise.
-MEASURED_TRAFFIC = {"sources_sha256_16": "57c90150be1eeeca", "bytes_per_launch": 7.821e9}
+# HBM traffic of one transfer call on this workload (traversal + projection
+# kernels), from two rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, scaled
+# by a 1 GiB copy): see profiles/direct_kernel_surface100k_hbm_counters.md.
+# Valid only for the kernel sources it was measured on (hash below); null
+# otherwise.
+MEASURED_TRAFFIC = {"sources_sha256_16": "446946ebf513149c", "bytes_per_launch": 1.018e10}
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
                   "paper_2408_03538_amd/csrc/common.hpp"]
 
@@ -165,7 +166,7 @@ def main():
     log(f"per traced ray: {n_box:.1f} box tests, {n_prim:.1f} Gaussian tests = {b_ray:.0f} algorithmic bytes; "
         f"{achieved:.0f} GB/s algorithmic")
     roofline = {
-        "kernel": "direct_kernel (visibility traversal + SH projection)",
+        "kernel": "direct_kernel + project_kernel (visibility traversal, then SH projection; one call)",
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": PEAK_HBM_GBS,
