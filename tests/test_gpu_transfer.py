@@ -183,6 +183,34 @@ def test_transfer_source_ranges(prt):
     assert torch.equal(full, part)
 
 
+def test_transfer_work_splits(prt, oracle_mod, monkeypatch):
+    """Every work split (the fan kernel, 2 to 64 sources per wave) gives the
+    same transfer up to the order in which a ray multiplies its hits' 1 - alpha
+    (the packets differ, so their visit orders do): the SH projection is one
+    FP64 sum per source in direction order whatever the split.  A ray whose
+    transmittance ends within rounding of T_eps may be cut off in one order
+    and not in another, moving one term by at most 4 pi / S T_eps |Y|."""
+    scene = as_f32(scenegen.surface_scene(4000, 21))
+    sc = prt.Scene.from_arrays(scene)
+    bvh = prt.build_bvh(sc)
+    S, bands = 128, 4
+    params = prt.TransferParams(num_dirs=S, sh_bands=bands)
+    outs = {}
+    for g in (1, 2, 8, 16, 64):
+        monkeypatch.setenv("PRTGS_GROUP", str(g))
+        outs[g] = prt.precompute_transfer(sc, bvh, params, check=True).cpu().numpy().astype(np.float64)
+    monkeypatch.delenv("PRTGS_GROUP")
+    ref = outs[8]
+    for g, t in outs.items():
+        d = np.abs(t - ref)
+        assert d.max() <= 4 * 4 * np.pi / S * params.T_eps, (g, d.max())
+        assert d.mean() <= 1e-7, (g, d.mean())
+    src = np.random.default_rng(22).choice(4000, 120, replace=False)
+    r = oracle_mod.direct_transfer(scene, S, bands, sources=src, want_allow=True)
+    for g, t in outs.items():
+        assert_transfer_parity(t[src, 0, :], r["t"], r["allow"])
+
+
 def test_transfer_degenerate(prt, oracle_mod):
     """A single splat sees an empty scene; coincident centres; tiny scales."""
     one = as_f32(scenegen.subset(scenegen.random_cloud(5, 1), [0]))
