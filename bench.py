@@ -47,6 +47,12 @@ FLOPS_PER_PRIM_TEST = 70
 # Valid only for the kernel sources it was measured on (hash below); null
 # otherwise.
 MEASURED_TRAFFIC = {"sources_sha256_16": "446946ebf513149c", "bytes_per_launch": 1.018e10}
+# VALU wave instructions of the traversal kernel per launch on this workload
+# (SQ_INSTS_VALU, profiles/direct_kernel_surface100k_sq_counters.md), valid
+# for the same sources; with the live launch time it gives the share of the
+# VALU issue slots the kernel uses (1024 SIMDs, 2.4 GHz, 4 cycles per wave64
+# instruction), which is what bounds it.
+MEASURED_VALU = {"sources_sha256_16": "446946ebf513149c", "instructions_per_launch": 1.392e10}
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
                   "paper_2408_03538_amd/csrc/common.hpp"]
 
@@ -180,6 +186,10 @@ def main():
         "algorithmic_bytes_per_unit": round(b_ray, 1),
         "per_ray": {"box_tests": round(n_box, 2), "prim_tests": round(n_prim, 2)},
         "ms_per_launch": round(t_kernel, 4),
+        "valu_issue": ({"instructions_per_launch": MEASURED_VALU["instructions_per_launch"],
+                        "busy_frac": round(MEASURED_VALU["instructions_per_launch"]
+                                           / (1024 * 2.4e9 / 4 * t_kernel * 1e-3), 3)}
+                       if kernel_sources_hash() == MEASURED_VALU["sources_sha256_16"] else None),
         "alu_view": {"algorithmic_flops_per_ray": round(f_ray, 1),
                      "achieved_TFLOPs": round(rays_per_s * f_ray / 1e12, 3), "peak_TFLOPs": PEAK_FP32_TFLOPS,
                      "packet_node_visits_per_64_rays": round(stats["wave_node_visits"] / (traced / 64), 1),
