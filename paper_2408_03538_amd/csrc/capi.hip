@@ -101,14 +101,14 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     if (d.bounces) off += align256(sizeof(float) * (size_t)n * (size_t)d.num_dirs);
     w.queue = off;
     if (d.bounces) off += 256;
-    w.hitkey = off;
-    if (d.bounces) off += align256((size_t)bounce_waves(n) * kHitList * 64 * 8);
-    w.hitalpha = off;
-    if (d.bounces) off += align256((size_t)bounce_waves(n) * kHitList * 64 * 4);
     // index mode: the index matrix and two bounce terms [n][3][K] (ping-pong)
     const bool idx = d.bounces && d.bounce_mode == PRTGS_BOUNCE_INDEX;
+    w.hitkey = off;
+    if (d.bounces) off += align256((size_t)bounce_waves(n, idx) * kHitList * 64 * 8);
+    w.hitalpha = off;
+    if (d.bounces) off += align256((size_t)bounce_waves(n, idx) * kHitList * 64 * 4);
     w.hitrec = off;
-    if (d.bounces && !idx) off += align256((size_t)bounce_waves(n) * kHitList * 64 * 8);
+    if (d.bounces && !idx) off += align256((size_t)bounce_waves(n, false) * kHitList * 64 * 8);
     w.index = off;
     if (idx) off += align256(sizeof(int32_t) * (size_t)n * (size_t)d.num_dirs);
     w.term0 = off;

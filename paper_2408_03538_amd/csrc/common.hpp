@@ -13,7 +13,8 @@ constexpr int kWave = 64;                 // CDNA wavefront width
 constexpr float kBoxSigma = 3.0f;         // BVH boxes enclose the 3-sigma ellipsoid
 constexpr size_t kFlagBytes = 256;        // flag word + padding at the head of a workspace
 constexpr int kHitList = 256;             // bounce: hits listed per ray and round
-constexpr int kBounceWaves = 4096;        // bounce: persistent waves (at most)
+constexpr int kBounceWavesPerSimd = 4;    // bounce (blend): resident waves per SIMD
+constexpr int kIndexWavesPerSimd = 5;     // bounce (index matrix): resident waves per SIMD
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -165,9 +166,14 @@ hipError_t launch_self_transfer(int n, int S, int K, const float* dirs, const fl
                                 const int32_t* index, const float* t_prev, int c_prev, float* t_out, unsigned* flags,
                                 hipStream_t stream);
 hipError_t launch_add(float* acc, const float* x, size_t count, hipStream_t stream);
-// Persistent waves of the bounce launch for n sources (any group size): the
-// hit-list scratch holds this many waves.
-inline int bounce_waves(int n) { return n < kBounceWaves ? n : kBounceWaves; }
+// Persistent waves of the bounce launch for n sources (any group size): as
+// many as the 1024 SIMDs hold at the kernel's occupancy; the hit-list scratch
+// holds this many waves.
+__host__ __device__ inline int bounce_waves(int n, bool index)
+{
+    const int cap = 1024 * (index ? kIndexWavesPerSimd : kBounceWavesPerSimd);
+    return n < cap ? n : cap;
+}
 
 struct BackwardArgs {
     TransferArgs fwd;

@@ -302,21 +302,24 @@ __device__ inline int key_j(uint64_t k) { return (int)(uint32_t)k; }
 // persistent: a fixed set of waves takes groups of sources from a counter,
 // so the lists are sized by the waves, not the scene.
 constexpr int kBlend = 8;   // hits selected per pass over the list
-constexpr int kScan = 8;    // list entries loaded together
 constexpr int kCheck = 8;   // depth checkpoints per ray and round
 
 // kIndex: the paper's own bounce instead of the blend -- the same walk, but
 // each ray records the hit of largest alpha_j T_j max(-w . n_j, 0) among the
 // hits with T_j <= t_same (the nearer one on equal weights) in the index
-// matrix (-1: none, or not traced), and nothing is accumulated.
-template <int K, bool kIndex>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void bounce_kernel(TransferArgs a)
+// matrix (-1: none, or not traced), and nothing is accumulated.  kScan list
+// entries are loaded together in the selection.
+template <int K, bool kIndex, int kScan>
+__device__ __forceinline__ void bounce_walk(const TransferArgs& a)
 {
     constexpr int M = kHitList;
     const int lane = threadIdx.x & (kWave - 1);
     const int G = a.G;
     const int D = kWave / G;
     const int wslot = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+    // the grid is whole blocks: a wave past the lists' capacity has none and
+    // leaves before it takes work (no block-wide barrier follows)
+    if (wslot >= bounce_waves(a.n, kIndex)) return;
     uint64_t* const lkey = a.hitkey + (size_t)wslot * M * kWave + lane;   // entry q at [q * kWave]
     float* const lalpha = a.hitalpha + (size_t)wslot * M * kWave + lane;
     int2* const lrec = kIndex ? nullptr : a.hitrec + (size_t)wslot * M * kWave + lane;
@@ -588,6 +591,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
 }
 
+// The two modes hold different registers at their peak (the blend its 3K
+// sums, the index mode none), so each gets the occupancy and scan width that
+// measured fastest: the blend 4 waves per SIMD and 8 entries per step, the
+// index walk 5 waves and 4 entries (a few cold spills in both).
+template <int K>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceWavesPerSimd))) void bounce_kernel(
+    TransferArgs a)
+{
+    bounce_walk<K, false, 8>(a);
+}
+template <int K>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kIndexWavesPerSimd))) void index_kernel(
+    TransferArgs a)
+{
+    bounce_walk<K, true, 4>(a);
+}
+
 // ---------------------------------------------------------------------------
 // the paper's recursive self-transfer: one gather step over the index matrix
 // (one wave per source, lanes over directions, then a wave reduction)
@@ -679,9 +699,13 @@ hipError_t launch_bounce_k(const TransferArgs& a, hipStream_t stream)
     hipError_t e = fill_u32(a.queue, 0u, 1, stream);
     if (e != hipSuccess) return e;
     const int groups = (a.count + a.G - 1) / a.G;
-    const int waves = groups < bounce_waves(a.n) ? groups : bounce_waves(a.n);   // the hit lists hold this many
-    hipLaunchKernelGGL((bounce_kernel<K, kIndex>), dim3((waves + kBlock / kWave - 1) / (kBlock / kWave)),
-                       dim3(kBlock), 0, stream, a);
+    const int cap = bounce_waves(a.n, kIndex);   // the hit lists hold this many
+    const int waves = groups < cap ? groups : cap;
+    const dim3 grid((waves + kBlock / kWave - 1) / (kBlock / kWave));
+    if constexpr (kIndex)
+        hipLaunchKernelGGL(index_kernel<K>, grid, dim3(kBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL(bounce_kernel<K>, grid, dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -39,6 +39,29 @@ def test_bounce_parity_sampled(prt, oracle_mod, S, bands):
     print(f"bounce max |dt| = {err:.2e}, max |t_ind| = {np.abs(ref['t_ind']).max():.3f}")
 
 
+@pytest.mark.parametrize("n_surface", [901, 1902])
+def test_bounce_source_count_not_whole_blocks(prt, oracle_mod, n_surface):
+    """Source counts (1201, 2202) whose persistent bounce launch does not
+    fill its last block of 4 waves: the spare waves hold no hit lists and must
+    take no work.  Blend and index matrix against the oracle, flags clear."""
+    scene = as_f32(scenegen._concat([scenegen.surface_scene(n_surface, 31), scenegen.shells(1, 300, 32)]))
+    n = scene["means"].shape[0]
+    assert n % 4 != 0
+    S, bands = 32, 3
+    sc = prt.Scene.from_arrays(scene)
+    bvh = prt.build_bvh(sc, check=True)
+    t = prt.precompute_transfer(sc, bvh, prt.TransferParams(num_dirs=S, sh_bands=bands, bounces=1),
+                                check=True).cpu().numpy()
+    src = np.random.default_rng(5).choice(n, 80, replace=False)
+    ref = oracle_mod.full_transfer(scene, S, bands, 1, sources=src, want_allow=True)
+    assert_transfer_parity(t[src], ref["t"], ref["allow"], what="bounce transfer")
+    params = prt.TransferParams(num_dirs=S, sh_bands=bands, bounce_mode="index", bounces=1)
+    idx = prt.index_matrix(sc, bvh, params, check=True).cpu().numpy()
+    ref_idx, amb = oracle_mod.index_matrix(scene, S, t_same=params.t_same, sources=src)
+    assert np.array_equal(idx[src][~amb], ref_idx[~amb])
+    assert ((idx >= -1) & (idx < n)).all()
+
+
 def test_bounce_many_faint_hits(prt, oracle_mod):
     """A crowded, faint cloud: rays meet hundreds of Gaussians before the
     transmittance falls below T_eps (or never do), so each ray needs several
