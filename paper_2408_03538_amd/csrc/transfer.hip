@@ -291,7 +291,8 @@ __device__ inline int key_j(uint64_t k) { return (int)(uint32_t)k; }
 // of the lane's own in device memory, unsorted (the traversal meets them in
 // no useful order).  Afterwards the lane blends the list nearest first,
 // kBlend hits at a time: one pass over the list (coalesced across the wave)
-// keeps the kBlend nearest unblended keys in a sorted register buffer, and
+// keeps the kBlend nearest unblended keys in a sorted register buffer
+// (merge_chunk folds in kScan entries at a time), and
 // each blended hit's weight goes to a per-lane record list; the records are
 // summed into the transfer once the round's selection is over, so that the
 // 3K sums are not live during the traversal or the scans.  A
@@ -303,6 +304,52 @@ __device__ inline int key_j(uint64_t k) { return (int)(uint32_t)k; }
 // so the lists are sized by the waves, not the scene.
 constexpr int kBlend = 8;   // hits selected per pass over the list
 constexpr int kCheck = 8;   // depth checkpoints per ray and round
+
+// Compare-exchange of two (key, alpha) pairs: the smaller key ends in a.
+__device__ inline void cas_pair(uint64_t& ka, float& aa, uint64_t& kb, float& ab)
+{
+    const bool sw = kb < ka;
+    const uint64_t tk = ka;
+    const float ta = aa;
+    ka = sw ? kb : ka;
+    aa = sw ? ab : aa;
+    kb = sw ? tk : kb;
+    ab = sw ? ta : ab;
+}
+
+// Folds a chunk of N keys (ineligible ones set to kNoHit) into the sorted
+// buffer of the kBlend = 8 smallest: a sorting network orders the chunk
+// (Batcher's odd-even merge sort), the buffer followed by the chunk reversed
+// is bitonic, so one half-cleaner step leaves the 8 smallest of both in the
+// buffer, and the bitonic merge network sorts them.  34 VALU per entry at
+// N = 8 against 56 for an insertion into the buffer, which one lane or
+// another needs at almost every entry.
+template <int N>
+__device__ inline void merge_chunk(uint64_t (&kk)[N], float (&aa)[N], uint64_t (&bk)[kBlend], float (&ba)[kBlend])
+{
+    static_assert(kBlend == 8 && (N == 4 || N == 8), "networks for 4 or 8 entries into 8");
+    auto c = [&](int i, int j) { cas_pair(kk[i], aa[i], kk[j], aa[j]); };
+    if constexpr (N == 4) {
+        c(0, 1); c(2, 3); c(0, 2); c(1, 3); c(1, 2);
+    } else {
+        c(0, 1); c(2, 3); c(4, 5); c(6, 7);
+        c(0, 2); c(1, 3); c(4, 6); c(5, 7);
+        c(1, 2); c(5, 6);
+        c(0, 4); c(1, 5); c(2, 6); c(3, 7);
+        c(2, 4); c(3, 5);
+        c(1, 2); c(3, 4); c(5, 6);
+    }
+#pragma unroll
+    for (int q = kBlend - N; q < kBlend; ++q) {
+        const bool lt = kk[kBlend - 1 - q] < bk[q];
+        bk[q] = lt ? kk[kBlend - 1 - q] : bk[q];
+        ba[q] = lt ? aa[kBlend - 1 - q] : ba[q];
+    }
+    auto b = [&](int i, int j) { cas_pair(bk[i], ba[i], bk[j], ba[j]); };
+    b(0, 4); b(1, 5); b(2, 6); b(3, 7);
+    b(0, 2); b(1, 3); b(4, 6); b(5, 7);
+    b(0, 1); b(2, 3); b(4, 5); b(6, 7);
+}
 
 // kIndex: the paper's own bounce instead of the blend -- the same walk, but
 // each ray records the hit of largest alpha_j T_j max(-w . n_j, 0) among the
@@ -475,27 +522,16 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a)
                             kk[u] = inl ? lkey[q * kWave] : kNoHit;
                             aa[u] = inl ? lalpha[q * kWave] : 0.0f;
                         }
+                        bool anysel = false;
 #pragma unroll
                         for (int u = 0; u < kScan; ++u) {
                             const uint64_t k = kk[u];
                             const bool sel = (k != kNoHit) & (!started | (k > k_last)) & (k < k_over) &
                                              (k < bk[kBlend - 1]);
-                            if (__ballot(sel) != 0ull) {
-                                // sorted insertion; lanes without a key carry kNoHit
-                                uint64_t ck = sel ? k : kNoHit;
-                                float ca = aa[u];
-#pragma unroll
-                                for (int q2 = 0; q2 < kBlend; ++q2) {
-                                    const bool lt = ck < bk[q2];
-                                    const uint64_t tk = bk[q2];
-                                    const float ta = ba[q2];
-                                    bk[q2] = lt ? ck : tk;
-                                    ba[q2] = lt ? ca : ta;
-                                    ck = lt ? tk : ck;
-                                    ca = lt ? ta : ca;
-                                }
-                            }
+                            kk[u] = sel ? k : kNoHit;
+                            anysel |= sel;
                         }
+                        if (__ballot(anysel) != 0ull) merge_chunk<kScan>(kk, aa, bk, ba);
                     }
                     int got = 0;
 #pragma unroll
