@@ -46,13 +46,13 @@ FLOPS_PER_PRIM_TEST = 70
 # by a 1 GiB copy): see profiles/direct_kernel_surface100k_hbm_counters.md.
 # Valid only for the kernel sources it was measured on (hash below); null
 # otherwise.
-MEASURED_TRAFFIC = {"sources_sha256_16": "edcaed455983cee3", "bytes_per_launch": 1.018e10}
+MEASURED_TRAFFIC = {"sources_sha256_16": "b082491267eeb9b4", "bytes_per_launch": 1.018e10}
 # VALU wave instructions of the traversal kernel per launch on this workload
 # (SQ_INSTS_VALU, profiles/direct_kernel_surface100k_sq_counters.md), valid
 # for the same sources; with the live launch time it gives the share of the
 # VALU issue slots the kernel uses (1024 SIMDs, 2.4 GHz, 4 cycles per wave64
 # instruction), which is what bounds it.
-MEASURED_VALU = {"sources_sha256_16": "edcaed455983cee3", "instructions_per_launch": 1.392e10}
+MEASURED_VALU = {"sources_sha256_16": "b082491267eeb9b4", "instructions_per_launch": 1.392e10}
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
                   "paper_2408_03538_amd/csrc/common.hpp"]
 
