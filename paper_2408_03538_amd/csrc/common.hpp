@@ -157,6 +157,8 @@ struct TransferArgs {
     int32_t* index;         // index mode: [n][S] argmax hit (original index), or null
     float t_same;           // index mode: same-surface filter threshold
     int G;                  // sources per wave (group split); 1 = fan kernel
+    int Q;                  // group split: waves per source group, each taking a
+                            // contiguous share of the direction batches (part-major)
     unsigned* flags;
 };
 hipError_t launch_transfer_direct(const TransferArgs& a, hipStream_t stream, unsigned long long* stats = nullptr);

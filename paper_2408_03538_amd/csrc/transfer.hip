@@ -7,12 +7,16 @@
 // directions at a time, consecutive in the coherent direction order (8 x 8
 // stratum tiles, Morton order inside, so aligned runs stay in one octant and
 // a compact patch of the sphere); lane l traces source l / D along direction
-// l % D.  Neighbouring origins share the Gaussians around them, nearby
+// l % D.  The direction batches of a group are shared among Q waves, issued
+// part-major, so that the waves in flight trace the same directions.  Neighbouring origins share the Gaussians around them, nearby
 // directions share the far field.  Each ray's weight T max(n . w, 0) is
 // stored, and a second kernel projects every source's S weights onto SH in
 // FP64, in direction order, so the transfer does not depend on the split.
 // Small scenes use the "fan" split instead (one source per wave, its
 // hemisphere directions compacted over the lanes) to fill the GPU.
+#include <algorithm>
+#include <cstdlib>
+
 #include "trace.hpp"
 
 namespace prtgs {
@@ -84,9 +88,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     const int lane = threadIdx.x & (kWave - 1);
     const int G = a.G;
     const int D = kWave / G;
-    const int gwave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-    const int local = gwave * G + lane / D;
-    const bool valid = local < a.count;
+    const int gwave = (int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
+    // part-major: wave w takes direction part w / groups of source group
+    // w % groups (spare waves of the last block get part >= Q: no work)
+    const int groups = (a.count + G - 1) / G;
+    const int part = gwave / groups;
+    const int local = (gwave % groups) * G + lane / D;
+    const bool valid = local < a.count && part < a.Q;
     const int rank = a.first + (valid ? local : 0);
     const float4 mo = a.prims[rank].mo;
     const float ox = mo.x, oy = mo.y, oz = mo.z;
@@ -95,7 +103,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     const HitParams hp = a.hp;
     RayCounts cnt;
     uint32_t traced_rays = 0;
-    for (int b0 = 0; b0 < a.S; b0 += D) {
+    const int nb = (a.S + D - 1) / D;
+    for (int bi = part * nb / a.Q; bi < (part + 1) * nb / a.Q; ++bi) {
+        const int b0 = bi * D;
         const int pos = b0 + (lane % D);
         const bool inrange = pos < a.S;
         const int s = inrange ? a.dir_order[pos] : 0;
@@ -704,24 +714,47 @@ __global__ void add_kernel(float* __restrict__ acc, const float* __restrict__ x,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-int group_blocks(int count, int G)
+int group_blocks(int count, int G, int Q = 1)
 {
-    int waves = (count + G - 1) / G;
-    return (waves + kBlock / kWave - 1) / (kBlock / kWave);
+    const int64_t waves = (int64_t)((count + G - 1) / G) * Q;
+    return (int)((waves + kBlock / kWave - 1) / (kBlock / kWave));
+}
+
+// Direction parts of the direct pass: the S directions of a source group are
+// split into Q contiguous runs of batches, one wave each, and the waves take
+// them part-major (every group's first part, then every group's second ...).
+// The thousands of waves resident together then trace nearly the same
+// directions from different sources: they walk the tree in the same order,
+// so its hot nodes stay in L2, and every XCD (blocks go to the 8 XCDs in
+// turn) gets every part, also where many directions fall below the surfaces'
+// horizon.  Measured at 100k x 256: Q = 1, 4, 8, 32 give 31.8, 23.4, 21.1,
+// 19.4 ms; at 1M x 512 Q = 1, 8, 32, 128: 1021, 935, 934, 938 ms.  One batch
+// per wave, at most 32 parts.
+int direction_parts(int G, int S)
+{
+    const int batches = (S + kWave / G - 1) / (kWave / G);
+    int Q = std::min(batches, 32);
+    if (const char* env = getenv("PRTGS_DPARTS")) {
+        const int q = atoi(env);
+        if (q >= 1 && q <= batches) Q = q;
+    }
+    return std::max(Q, 1);
 }
 
 template <int K>
 hipError_t launch_direct_k(const TransferArgs& a, unsigned long long* stats, hipStream_t stream)
 {
+    TransferArgs b = a;
+    b.Q = a.G == 1 ? 1 : direction_parts(a.G, a.S);
     if (stats) {
-        hipLaunchKernelGGL((direct_kernel<true>), dim3(group_blocks(a.count, a.G)), dim3(kBlock), 0, stream, a,
+        hipLaunchKernelGGL((direct_kernel<true>), dim3(group_blocks(a.count, a.G, b.Q)), dim3(kBlock), 0, stream, b,
                            stats);
         return hipGetLastError();
     }
     if (a.G == 1)
-        hipLaunchKernelGGL(direct_fan_kernel, dim3(group_blocks(a.count, 1)), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL(direct_fan_kernel, dim3(group_blocks(a.count, 1)), dim3(kBlock), 0, stream, b);
     else
-        hipLaunchKernelGGL((direct_kernel<false>), dim3(group_blocks(a.count, a.G)), dim3(kBlock), 0, stream, a,
+        hipLaunchKernelGGL((direct_kernel<false>), dim3(group_blocks(a.count, a.G, b.Q)), dim3(kBlock), 0, stream, b,
                            stats);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
