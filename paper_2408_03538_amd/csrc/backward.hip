@@ -76,9 +76,13 @@ __global__ __launch_bounds__(kBlock) void transfer_backward_kernel(BackwardArgs 
     const int lane = threadIdx.x & (kWave - 1);
     const int G = a.G;
     const int D = kWave / G;
-    const int gwave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-    const int local = gwave * G + lane / D;
-    const bool valid = local < a.count;
+    // direction parts taken part-major, as in the forward pass (spare waves
+    // of the last block get part >= Q: no work)
+    const int gwave = (int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
+    const int groups = (a.count + G - 1) / G;
+    const int part = gwave / groups;
+    const int local = (gwave % groups) * G + lane / D;
+    const bool valid = local < a.count && part < a.Q;
     const int rank = valid ? local : 0;
     const float4 mo = a.prims[rank].mo;
     const float ox = mo.x, oy = mo.y, oz = mo.z;
@@ -93,7 +97,9 @@ __global__ __launch_bounds__(kBlock) void transfer_backward_kernel(BackwardArgs 
     float gni[3] = {0.0f, 0.0f, 0.0f};   // dLoss/dn_i
     const float wq = kFourPi / (float)a.S;
 
-    for (int b0 = 0; b0 < a.S; b0 += D) {
+    const int nb = (a.S + D - 1) / D;
+    for (int bi = part * nb / a.Q; bi < (part + 1) * nb / a.Q; ++bi) {
+        const int b0 = bi * D;
         const int pos = b0 + (lane % D);
         const bool inrange = pos < a.S;
         const int s = inrange ? a.dir_order[pos] : 0;
@@ -197,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void transfer_backward_kernel(BackwardArgs 
     if (!valid || (lane % D) != 0) return;
     for (int q = 0; q < 3; ++q) {
         atomicAdd(&ba.g_mu[3 * (size_t)rank + q], gmi[q]);
-        ba.g_n[3 * (size_t)rank + q] = gni[q];
+        atomicAdd(&ba.g_n[3 * (size_t)rank + q], gni[q]);   // the source's other parts add theirs
     }
 }
 
@@ -253,12 +259,14 @@ __global__ void backward_finalize_kernel(BackwardArgs ba)
 template <int K>
 hipError_t launch_bwd_k(const BackwardArgs& a, hipStream_t stream)
 {
-    int waves = (a.fwd.count + a.fwd.G - 1) / a.fwd.G;
-    int blocks = (waves + kBlock / kWave - 1) / (kBlock / kWave);
-    hipLaunchKernelGGL(transfer_backward_kernel<K>, dim3(blocks), dim3(kBlock), 0, stream, a);
+    BackwardArgs b = a;
+    b.fwd.Q = direction_parts(a.fwd.G, a.fwd.S);
+    const int64_t waves = (int64_t)((a.fwd.count + a.fwd.G - 1) / a.fwd.G) * b.fwd.Q;
+    const int blocks = (int)((waves + kBlock / kWave - 1) / (kBlock / kWave));
+    hipLaunchKernelGGL(transfer_backward_kernel<K>, dim3(blocks), dim3(kBlock), 0, stream, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(backward_finalize_kernel, dim3((a.fwd.n + 255) / 256), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(backward_finalize_kernel, dim3((a.fwd.n + 255) / 256), dim3(256), 0, stream, b);
     return hipGetLastError();
 }
 

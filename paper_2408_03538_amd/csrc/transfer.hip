@@ -14,9 +14,6 @@
 // FP64, in direction order, so the transfer does not depend on the split.
 // Small scenes use the "fan" split instead (one source per wave, its
 // hemisphere directions compacted over the lanes) to fill the GPU.
-#include <algorithm>
-#include <cstdlib>
-
 #include "trace.hpp"
 
 namespace prtgs {
@@ -718,27 +715,6 @@ int group_blocks(int count, int G, int Q = 1)
 {
     const int64_t waves = (int64_t)((count + G - 1) / G) * Q;
     return (int)((waves + kBlock / kWave - 1) / (kBlock / kWave));
-}
-
-// Direction parts of the direct pass: the S directions of a source group are
-// split into Q contiguous runs of batches, one wave each, and the waves take
-// them part-major (every group's first part, then every group's second ...).
-// The thousands of waves resident together then trace nearly the same
-// directions from different sources: they walk the tree in the same order,
-// so its hot nodes stay in L2, and every XCD (blocks go to the 8 XCDs in
-// turn) gets every part, also where many directions fall below the surfaces'
-// horizon.  Measured at 100k x 256: Q = 1, 4, 8, 32 give 31.8, 23.4, 21.1,
-// 19.4 ms; at 1M x 512 Q = 1, 8, 32, 128: 1021, 935, 934, 938 ms.  One batch
-// per wave, at most 32 parts.
-int direction_parts(int G, int S)
-{
-    const int batches = (S + kWave / G - 1) / (kWave / G);
-    int Q = std::min(batches, 32);
-    if (const char* env = getenv("PRTGS_DPARTS")) {
-        const int q = atoi(env);
-        if (q >= 1 && q <= batches) Q = q;
-    }
-    return std::max(Q, 1);
 }
 
 template <int K>
