@@ -171,7 +171,8 @@ prtgs_status prtgs_bvh_leaf_order(const void* bvh, int32_t n, int32_t* order /* 
 /* of per-ray weights (2 GiB at 1M x 512); with a bounce also 4 n S bytes   */
 /* of per-ray cut depths and the per-lane hit lists of the persistent      */
 /* waves: min(n, 4096) waves and 768 MiB of lists + 512 MiB of hit records */
-/* for the blend, min(n, 5120) waves and 960 MiB of lists in index mode.   */
+/* + 1536 n bytes of per-part bounce sums (at K = 16) for the blend,        */
+/* min(n, 5120) waves and 960 MiB of lists in index mode.                   */
 /* ---------------------------------------------------------------------- */
 size_t prtgs_transfer_workspace_bytes(const prtgs_transfer_desc* d /* host */, int32_t n);
 prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g /* host */, const void* bvh,

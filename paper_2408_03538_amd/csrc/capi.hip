@@ -77,7 +77,8 @@ prtgs_status check_desc(const prtgs_transfer_desc* d)
 }
 
 struct TransferWs {
-    size_t dirs, Y, dir_order, rayw, tdir, albedo, tcut, queue, hitkey, hitalpha, hitrec, index, term0, term1, total;
+    size_t dirs, Y, dir_order, rayw, tdir, albedo, tcut, queue, hitkey, hitalpha, hitrec, partial, index, term0, term1,
+        total;
 };
 
 TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
@@ -109,6 +110,8 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     if (d.bounces) off += align256((size_t)bounce_waves(n, idx) * kHitList * 64 * 4);
     w.hitrec = off;
     if (d.bounces && !idx) off += align256((size_t)bounce_waves(n, false) * kHitList * 64 * 8);
+    w.partial = off;
+    if (d.bounces && !idx) off += align256(sizeof(float) * kBlendPartsMax * 3 * (size_t)K * (size_t)n);
     w.index = off;
     if (idx) off += align256(sizeof(int32_t) * (size_t)n * (size_t)d.num_dirs);
     w.term0 = off;
@@ -250,6 +253,7 @@ TransferArgs transfer_args(const prtgs_gaussians* g, const void* bvh, const prtg
     a.hitkey = bounce ? reinterpret_cast<uint64_t*>(w + W.hitkey) : nullptr;
     a.hitalpha = bounce ? reinterpret_cast<float*>(w + W.hitalpha) : nullptr;
     a.hitrec = bounce && d->bounce_mode == PRTGS_BOUNCE_BLEND ? reinterpret_cast<int2*>(w + W.hitrec) : nullptr;
+    a.partial = bounce && d->bounce_mode == PRTGS_BOUNCE_BLEND ? reinterpret_cast<float*>(w + W.partial) : nullptr;
     a.index = nullptr;
     a.t_same = d->t_same;
     a.G = group_size(count);

@@ -18,6 +18,7 @@ constexpr size_t kFlagBytes = 256;        // flag word + padding at the head of 
 constexpr int kHitList = 256;             // bounce: hits listed per ray and round
 constexpr int kBounceWavesPerSimd = 4;    // bounce (blend): resident waves per SIMD
 constexpr int kIndexWavesPerSimd = 5;     // bounce (index matrix): resident waves per SIMD
+constexpr int kBlendPartsMax = 8;         // bounce (blend): direction parts with sums of their own
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -148,6 +149,8 @@ struct TransferArgs {
     float4* albedo_sorted;  // [n] leaf order (bounce scratch), or null
     uint64_t* hitkey;       // bounce: per-lane hit lists of the persistent waves,
     float* hitalpha;        // [wave][kHitList][64] keys (t bits, leaf rank) and alphas
+    float* partial;         // blend: [kBlendPartsMax][n][3][K] each direction part's
+                            // bounce sums, added into transfer in part order
     int2* hitrec;           // blend: [wave][kHitList][64] (leaf rank, weight) of the
                             // hits blended in the current round, in blend order
     unsigned* queue;        // bounce: work counter (zeroed before the launch)

@@ -383,10 +383,13 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a)
     const int max_rounds = a.n + 1;
 
     for (;;) {
-        int grp = 0;
-        if (lane == 0) grp = (int)atomicAdd(a.queue, 1u);
-        grp = __builtin_amdgcn_readfirstlane(grp);
-        if (grp >= groups) break;   // uniform: every wave leaves once the counter passes the last group
+        // items are (direction part, source group), taken part-major as in the
+        // direct pass, so the waves in flight trace nearly the same directions
+        int item = 0;
+        if (lane == 0) item = (int)atomicAdd(a.queue, 1u);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= groups * a.Q) break;   // uniform: every wave leaves once the counter passes the last item
+        const int part = item / groups, grp = item % groups;
 
         const int local = grp * G + lane / D;
         const bool valid = local < a.count;
@@ -397,7 +400,9 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a)
         const int orig = valid ? a.order[rank] : 0;
         const float scale = kFourPi / (float)a.S;
 
-        for (int b0 = 0; b0 < a.S; b0 += D) {
+        const int nb = (a.S + D - 1) / D;
+        for (int bi = part * nb / a.Q; bi < (part + 1) * nb / a.Q; ++bi) {
+            const int b0 = bi * D;
             const int pos = b0 + (lane % D);
             const bool inrange = pos < a.S;
             const int s = inrange ? a.dir_order[pos] : 0;
@@ -620,7 +625,8 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a)
                     }
 #pragma unroll
                     for (int ch = 0; ch < 3; ++ch) {
-                        float* out = a.transfer + ((size_t)orig * 3 + ch) * K;
+                        // this part's own sums (one wave owns a (part, source) pair)
+                        float* out = a.partial + (((size_t)part * a.n + orig) * 3 + ch) * K;
 #pragma unroll
                         for (int k = 0; k < K; ++k) {
                             const float v = segment_sum(acc[ch][k], D) * scale;
@@ -702,6 +708,16 @@ __global__ __launch_bounds__(kBlock) void self_transfer_kernel(int n, int S, con
     if (lane < 3 * K) t_out[(size_t)i * 3 * K + lane] = mine * scale;
 }
 
+// transfer += the parts' bounce sums, added in part order
+__global__ void add_parts_kernel(float* __restrict__ acc, const float* __restrict__ parts, size_t count, int Q)
+{
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
+        float v = acc[e];
+        for (int q = 0; q < Q; ++q) v += parts[(size_t)q * count + e];
+        acc[e] = v;
+    }
+}
+
 __global__ void add_kernel(float* __restrict__ acc, const float* __restrict__ x, size_t count)
 {
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
@@ -743,14 +759,28 @@ hipError_t launch_bounce_k(const TransferArgs& a, hipStream_t stream)
 {
     hipError_t e = fill_u32(a.queue, 0u, 1, stream);
     if (e != hipSuccess) return e;
-    const int groups = (a.count + a.G - 1) / a.G;
+    TransferArgs b = a;
+    b.Q = direction_parts(a.G, a.S);
+    if constexpr (!kIndex) {
+        // the blend keeps a set of sums per part: at most kBlendPartsMax parts
+        b.Q = std::min(b.Q, kBlendPartsMax);
+        e = fill_u32(reinterpret_cast<uint32_t*>(b.partial), 0u, (size_t)b.Q * a.n * 3 * a.K, stream);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t items = (int64_t)((a.count + a.G - 1) / a.G) * b.Q;
     const int cap = bounce_waves(a.n, kIndex);   // the hit lists hold this many
-    const int waves = groups < cap ? groups : cap;
+    const int waves = items < cap ? (int)items : cap;
     const dim3 grid((waves + kBlock / kWave - 1) / (kBlock / kWave));
-    if constexpr (kIndex)
-        hipLaunchKernelGGL(index_kernel<K>, grid, dim3(kBlock), 0, stream, a);
-    else
-        hipLaunchKernelGGL(bounce_kernel<K>, grid, dim3(kBlock), 0, stream, a);
+    if constexpr (kIndex) {
+        hipLaunchKernelGGL(index_kernel<K>, grid, dim3(kBlock), 0, stream, b);
+    } else {
+        hipLaunchKernelGGL(bounce_kernel<K>, grid, dim3(kBlock), 0, stream, b);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const size_t count = (size_t)a.n * 3 * a.K;
+        hipLaunchKernelGGL(add_parts_kernel, dim3((unsigned)std::min<size_t>((count + 255) / 256, 65536)), dim3(256), 0,
+                           stream, a.transfer, b.partial, count, b.Q);
+    }
     return hipGetLastError();
 }
 

@@ -128,17 +128,18 @@ def test_index_mode_workspace(lib):
     b = lib.prtgs_transfer_workspace_bytes(ctypes.byref(blend), 1000)
     i = lib.prtgs_transfer_workspace_bytes(ctypes.byref(index), 1000)
     lists = 1000 * 256 * 64 * (8 + 4)
-    assert b >= d + lists + 1000 * 256 * 64 * 8                # hit lists + hit records
+    assert b >= d + lists + 1000 * 256 * 64 * 8 + 8 * 1000 * 3 * 9 * 4   # hit lists + records + part sums
     assert i >= d + lists + 1000 * 64 * 4 + 2 * 1000 * 3 * 9 * 4   # hit lists + index matrix + two bounce terms
     assert i < d + lists + 1000 * 256 * 64 * 8                  # no hit records
     # past 4096 sources the blend's lists and records hold 4096 persistent waves
-    # (4 per SIMD), the index mode's lists 5120 (5 per SIMD)
+    # (4 per SIMD), the index mode's lists 5120 (5 per SIMD); the blend also
+    # keeps bounce sums for up to 8 direction parts
     n = 20000
     d = lib.prtgs_transfer_workspace_bytes(ctypes.byref(direct), n)
     b = lib.prtgs_transfer_workspace_bytes(ctypes.byref(blend), n)
     i = lib.prtgs_transfer_workspace_bytes(ctypes.byref(index), n)
     common = align(n * 9 * 4) + align(n * 16) + align(n * 64 * 4) + 256   # leaf-order transfer, albedo, cut depths, counter
-    assert b - d - common == align(4096 * 256 * 64 * 8) * 2 + align(4096 * 256 * 64 * 4)
+    assert b - d - common == align(4096 * 256 * 64 * 8) * 2 + align(4096 * 256 * 64 * 4) + align(8 * n * 3 * 9 * 4)
     assert i - d - common - align(n * 64 * 4) - 2 * align(n * 3 * 9 * 4) == \
         align(5120 * 256 * 64 * 8) + align(5120 * 256 * 64 * 4)
 
