@@ -46,13 +46,13 @@ FLOPS_PER_PRIM_TEST = 70
 # by a 1 GiB copy): see profiles/direct_kernel_surface100k_hbm_counters.md.
 # Valid only for the kernel sources it was measured on (hash below); null
 # otherwise.
-MEASURED_TRAFFIC = {"sources_sha256_16": "b082491267eeb9b4", "bytes_per_launch": 1.018e10}
+MEASURED_TRAFFIC = {"sources_sha256_16": "df3901f579e7791d", "bytes_per_launch": 6.268e9}
 # VALU wave instructions of the traversal kernel per launch on this workload
 # (SQ_INSTS_VALU, profiles/direct_kernel_surface100k_sq_counters.md), valid
 # for the same sources; with the live launch time it gives the share of the
-# VALU issue slots the kernel uses (1024 SIMDs, 2.4 GHz, 4 cycles per wave64
-# instruction), which is what bounds it.
-MEASURED_VALU = {"sources_sha256_16": "b082491267eeb9b4", "instructions_per_launch": 1.392e10}
+# VALU issue rate the kernel uses (1024 SIMDs at 2.4 GHz, one wave64 FP32
+# instruction per 2 cycles: the rate behind the 157.3 TFLOP/s FP32 peak).
+MEASURED_VALU = {"sources_sha256_16": "df3901f579e7791d", "instructions_per_launch": 1.405e10}
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
                   "paper_2408_03538_amd/csrc/common.hpp"]
 
@@ -188,7 +188,7 @@ def main():
         "ms_per_launch": round(t_kernel, 4),
         "valu_issue": ({"instructions_per_launch": MEASURED_VALU["instructions_per_launch"],
                         "busy_frac": round(MEASURED_VALU["instructions_per_launch"]
-                                           / (1024 * 2.4e9 / 4 * t_kernel * 1e-3), 3)}
+                                           / (1024 * 2.4e9 / 2 * t_kernel * 1e-3), 3)}
                        if kernel_sources_hash() == MEASURED_VALU["sources_sha256_16"] else None),
         "alu_view": {"algorithmic_flops_per_ray": round(f_ray, 1),
                      "achieved_TFLOPs": round(rays_per_s * f_ray / 1e12, 3), "peak_TFLOPs": PEAK_FP32_TFLOPS,
