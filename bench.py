@@ -54,7 +54,7 @@ MEASURED_TRAFFIC = {"sources_sha256_16": "df3901f579e7791d", "bytes_per_launch":
 # instruction per 2 cycles: the rate behind the 157.3 TFLOP/s FP32 peak).
 MEASURED_VALU = {"sources_sha256_16": "df3901f579e7791d", "instructions_per_launch": 1.405e10}
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
-                  "paper_2408_03538_amd/csrc/common.hpp"]
+                  "paper_2408_03538_amd/csrc/common.hpp", "paper_2408_03538_amd/csrc/capi.hip"]   # capi: work split
 
 
 def kernel_sources_hash():

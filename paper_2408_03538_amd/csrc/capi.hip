@@ -122,12 +122,15 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     return w;
 }
 
-// Sources per wave of the group split: as many as keep >= 8192 waves in
-// flight (256 CUs x 32), at most 16; 1 selects the fan kernel.
+// Sources per wave of the group split; 1 selects the fan kernel.  With the
+// direction batches spread over waves a launch holds ~count S / 64 waves
+// whatever G is, so G is chosen by measurement (S = 256 surface scenes):
+// 16 from 40k sources (50k: 6.2 ms against 6.7 for G = 8; 100k: 16.9 against
+// 19.5), 8 from 10k (20k: 1.9 against 2.0 for 16, 2.9 for 2), 4 from 2048
+// (5k: 0.61 against 0.89 for the fan kernel), the fan kernel below.
 int group_size(int count)
 {
-    int G = 16;
-    while (G > 1 && count / G < 8192) G >>= 1;
+    int G = count >= 40000 ? 16 : count >= 10000 ? 8 : count >= 2048 ? 4 : 1;
     if (const char* env = getenv("PRTGS_GROUP")) {
         int g = atoi(env);
         if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64) G = g;

@@ -169,9 +169,14 @@ def test_transfer_surface_sampled(prt, oracle_mod):
     assert_transfer_parity(t.cpu().numpy()[src, 0, :], ref["t"], ref["allow"])
 
 
-def test_transfer_source_ranges(prt):
-    """Chunked runs over leaf ranges reproduce the single run bit for bit."""
+@pytest.mark.parametrize("group", ["1", "4"])
+def test_transfer_source_ranges(prt, monkeypatch, group):
+    """Chunked runs over leaf ranges reproduce the single run bit for bit
+    under one work split (the fan kernel, 4 sources per wave; chunks of 700
+    keep the groups of 4 aligned).  Across splits only the order of each ray's
+    1 - alpha products differs: test_transfer_work_splits."""
     import torch
+    monkeypatch.setenv("PRTGS_GROUP", group)
     scene = as_f32(scenegen.random_cloud(3000, 12))
     sc = prt.Scene.from_arrays(scene)
     bvh = prt.build_bvh(sc)
