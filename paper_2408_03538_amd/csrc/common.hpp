@@ -181,13 +181,14 @@ hipError_t launch_add(float* acc, const float* x, size_t count, hipStream_t stre
 // directions from different sources: they walk the tree in the same order,
 // so its hot nodes stay in L2, and every XCD (blocks go to the 8 XCDs in
 // turn) gets every part, also where many directions fall below the surfaces'
-// horizon.  Measured at 100k x 256: Q = 1, 4, 8, 32 give 31.8, 23.4, 21.1,
-// 19.4 ms; at 1M x 512 Q = 1, 8, 32, 128: 1021, 935, 934, 938 ms.  One batch
-// per wave, at most 32 parts.
+// horizon.  Measured at 100k x 256 (8 sources per wave): Q = 1, 4, 8, 32
+// give 31.8, 23.4, 21.1, 19.4 ms; with 16 sources per wave Q = 16, 32, 64
+// give 18.1, 16.9, 16.3 ms; at 1M x 512 Q = 1, 8, 32, 128: 1021, 935, 934,
+// 938 ms.  One batch per wave, at most 64 parts.
 inline int direction_parts(int G, int S)
 {
     const int batches = (S + kWave / G - 1) / (kWave / G);
-    int Q = std::min(batches, 32);
+    int Q = std::min(batches, 64);
     if (const char* env = getenv("PRTGS_DPARTS")) {
         const int q = atoi(env);
         if (q >= 1 && q <= batches) Q = q;
