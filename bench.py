@@ -46,13 +46,13 @@ FLOPS_PER_PRIM_TEST = 70
 # by a 1 GiB copy): see profiles/direct_kernel_surface100k_hbm_counters.md.
 # Valid only for the kernel sources it was measured on (hash below); null
 # otherwise.
-MEASURED_TRAFFIC = {"sources_sha256_16": "6b01d26cd59f65b2", "bytes_per_launch": 7.830e9}
+MEASURED_TRAFFIC = {"sources_sha256_16": "11f86c8f31e409da", "bytes_per_launch": 7.273e9}
 # VALU wave instructions of the traversal kernel per launch on this workload
 # (SQ_INSTS_VALU, profiles/direct_kernel_surface100k_sq_counters.md), valid
 # for the same sources; with the live launch time it gives the share of the
 # VALU issue rate the kernel uses (1024 SIMDs at 2.4 GHz, one wave64 FP32
 # instruction per 2 cycles: the rate behind the 157.3 TFLOP/s FP32 peak).
-MEASURED_VALU = {"sources_sha256_16": "6b01d26cd59f65b2", "instructions_per_launch": 1.170e10}
+MEASURED_VALU = {"sources_sha256_16": "11f86c8f31e409da", "instructions_per_launch": 1.173e10}
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
                   "paper_2408_03538_amd/csrc/common.hpp", "paper_2408_03538_amd/csrc/capi.hip"]   # capi: work split
 
