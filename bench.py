@@ -1,18 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the PRTGS transfer precompute on one MI355X.
 
-A step is one pass of the hot path over the 100k-splat surface workload (a
-unit sphere on a 4x4 plane, 100,000 Gaussians, S = 256 directions, 16 SH
-coefficients, direct visibility transfer): BVH build, transfer precompute
-and relighting under one light.  `value` is nominal rays (N * S) per second
-of the whole step, inputs already resident on the GPU.  The same JSON line
-carries the secondary measurements: the million-splat workload with one
-interreflection bounce, relighting 3M splats x 64 lights with FP32 vs BF16 /
-F16 storage, forward vs forward + backward on 200k splats, and the CPU oracle
-baseline.
+A step is one pass of the hot path over the million-splat workload (a unit
+sphere on a 4x4 plane with 200,000 surface splats plus 20 ellipsoid shells of
+40,000 splats each: 1,000,000 Gaussians, S = 512 directions, 16 SH
+coefficients, RGB transfer with one interreflection bounce): BVH build, the
+direct pass, the bounce pass and relighting under one light.  `value` is
+nominal rays (N * S) per second of the whole step, inputs already resident on
+the GPU.  The same JSON line carries the per-pass breakdown, the roofline of
+the dominant kernel (the bounce walk), and the secondary measurements: the
+100k-splat surface workload (direct transfer only), the paper's index-matrix
+bounce, a relit 1080p frame, glossy matrices, relighting 3M splats x 64
+lights with FP32 vs BF16 / F16 storage, forward vs forward + backward on 200k
+splats, and the CPU oracle baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
     python bench.py --copy-mib M      # plain device copy (counter calibration)
+    python bench.py --million-only    # the headline step alone (for profiling)
     python bench.py --frame-only      # relit 1080p frames of the million-splat scene
     python bench.py --relight-only    # the 3M x 64 relight alone
 """
@@ -34,27 +38,31 @@ PEAK_BF16_TFLOPS = 2500.0
 
 # Algorithmic cost of single-ray traversal work: a child-box test reads one
 # FP32 box plus a reference (32 B) and costs ~15 flops; a Gaussian test reads
-# the minimal parameterisation mu, q, 1/s, o (44 B) and costs ~70 flops.
+# the minimal parameterisation mu, q, 1/s, o (44 B) and costs ~70 flops.  A
+# blended hit of the bounce reads the hit splat's direct transfer and albedo
+# (16 x 4 + 12 = 76 B at 16 coefficients).
 BYTES_PER_BOX_TEST = 32
 BYTES_PER_PRIM_TEST = 44
 FLOPS_PER_BOX_TEST = 15
 FLOPS_PER_PRIM_TEST = 70
 
-
-# HBM traffic of one transfer call on this workload (traversal + projection
-# kernels), from two rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, scaled
-# by a 1 GiB copy): see profiles/direct_kernel_surface100k_hbm_counters.md.
-# Valid only for the kernel sources it was measured on (hash below); null
-# otherwise.
-MEASURED_TRAFFIC = {"sources_sha256_16": "11f86c8f31e409da", "bytes_per_launch": 7.273e9}
-# VALU wave instructions of the traversal kernel per launch on this workload
-# (SQ_INSTS_VALU, profiles/direct_kernel_surface100k_sq_counters.md), valid
-# for the same sources; with the live launch time it gives the share of the
-# VALU issue rate the kernel uses (1024 SIMDs at 2.4 GHz, one wave64 FP32
-# instruction per 2 cycles: the rate behind the 157.3 TFLOP/s FP32 peak).
-MEASURED_VALU = {"sources_sha256_16": "11f86c8f31e409da", "instructions_per_launch": 1.173e10}
+# Counter measurements (rocprofv3 --pmc, one run per counter set; FETCH_SIZE
+# scaled by 2.0 and WRITE_SIZE by 1.0, the factors a 1 GiB copy reads), valid
+# only for the kernel sources they were measured on (hash below), else null.
+# direct: traversal + projection of the 100k surface workload
+# (profiles/direct_kernel_surface100k_hbm_counters.md,
+# profiles/direct_kernel_surface100k_sq_counters.md); bounce: bounce_kernel<16>
+# of the million-splat workload (profiles/bounce_kernel_million_counters.md).
+MEASURED = {
+    "direct_surface100k": {"sources_sha256_16": "11f86c8f31e409da", "bytes_per_launch": 7.273e9,
+                           "valu_instructions_per_launch": 1.173e10},
+    "bounce_million": {"sources_sha256_16": None, "bytes_per_launch": None, "valu_instructions_per_launch": None},
+}
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
                   "paper_2408_03538_amd/csrc/common.hpp", "paper_2408_03538_amd/csrc/capi.hip"]   # capi: work split
+# VALU issue rate: 1024 SIMDs at 2.4 GHz, one wave64 FP32 instruction per 2
+# cycles (the rate behind the 157.3 TFLOP/s FP32 peak)
+VALU_WAVE_INSTR_PER_S = 1024 * 2.4e9 / 2
 
 
 def kernel_sources_hash():
@@ -73,16 +81,20 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-extras", action="store_true", help="skip the relight and backward measurements")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-extras", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle baseline budget")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="CPU oracle baseline budget")
     ap.add_argument("--copy-mib", type=int, default=0, help="only run a plain device copy of this size")
+    ap.add_argument("--million-only", action="store_true",
+                    help="only the headline steps, with no statistics pass (profiling runs)")
     ap.add_argument("--frame-only", action="store_true",
                     help="only time relit 1080p frames of the million-splat scene (synthetic transfers)")
     ap.add_argument("--relight-only", action="store_true",
                     help="only time the 3M x 64 relight in FP32, BF16 and F16 storage")
+    ap.add_argument("--surface-only", action="store_true",
+                    help="only the 100k surface workload (direct transfer; profiling runs)")
     return ap.parse_args()
 
 
@@ -129,6 +141,12 @@ def copy_only(mib):
     print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}))
 
 
+def measured(key):
+    """A counter measurement, if it was taken on the current kernel sources."""
+    m = MEASURED[key]
+    return m if m["sources_sha256_16"] == kernel_sources_hash() else None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -152,83 +170,153 @@ def main():
     if args.relight_only:
         print(json.dumps({"relight_3m": bench_relight(prt, torch, scenegen, np, args.steps)}), flush=True)
         return
-    log("generating the 100k surface workload")
-    arr, sc, params, light = workload_setup(prt, torch, scenegen, "surface100k")
+    if args.surface_only:
+        print(json.dumps({"surface100k_direct": bench_surface100k(prt, torch, scenegen, np, args.steps,
+                                                                   args.warmup)}), flush=True)
+        return
+    log("generating the million-splat workload")
+    arr, sc, params, light = workload_setup(prt, torch, scenegen, "million")
     n, S = sc.n, params.num_dirs
     res = time_steps(prt, torch, np, sc, params, light, args.steps, args.warmup)
     ms_step = res["ms_step"]
-    log(f"step {ms_step:.2f} ms: build {res['build']:.3f} ms, transfer {res['transfer']:.2f} ms, "
+    log(f"step {ms_step:.1f} ms: build {res['build']:.2f} ms, transfer {res['transfer']:.1f} ms, "
         f"relight {res['relight']:.4f} ms")
-
-    stats = prt.traversal_stats(sc, res["bvh"], params)
-    traced = stats["traced_rays"]
-    n_box = stats["box_tests"] / traced
-    n_prim = stats["prim_tests"] / traced
-    b_ray = BYTES_PER_BOX_TEST * n_box + BYTES_PER_PRIM_TEST * n_prim
-    f_ray = FLOPS_PER_BOX_TEST * n_box + FLOPS_PER_PRIM_TEST * n_prim
-    t_kernel = res["transfer"]
-    rays_per_s = traced / (t_kernel * 1e-3)
-    achieved = rays_per_s * b_ray / 1e9
-    log(f"per traced ray: {n_box:.1f} box tests, {n_prim:.1f} Gaussian tests = {b_ray:.0f} algorithmic bytes; "
-        f"{achieved:.0f} GB/s algorithmic")
-    roofline = {
-        "kernel": "direct_kernel + project_kernel (visibility traversal, then SH projection; one call)",
-        "bound": "hbm",
-        "achieved": round(achieved, 1),
-        "peak": PEAK_HBM_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / PEAK_HBM_GBS, 4),
-        "traffic": (MEASURED_TRAFFIC["bytes_per_launch"]
-                    if kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"] else None),
-        "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-        "units_per_launch": traced,
-        "unit_of_work": "traced ray",
-        "algorithmic_bytes_per_unit": round(b_ray, 1),
-        "per_ray": {"box_tests": round(n_box, 2), "prim_tests": round(n_prim, 2)},
-        "ms_per_launch": round(t_kernel, 4),
-        "valu_issue": ({"instructions_per_launch": MEASURED_VALU["instructions_per_launch"],
-                        "busy_frac": round(MEASURED_VALU["instructions_per_launch"]
-                                           / (1024 * 2.4e9 / 2 * t_kernel * 1e-3), 3)}
-                       if kernel_sources_hash() == MEASURED_VALU["sources_sha256_16"] else None),
-        "alu_view": {"algorithmic_flops_per_ray": round(f_ray, 1),
-                     "achieved_TFLOPs": round(rays_per_s * f_ray / 1e12, 3), "peak_TFLOPs": PEAK_FP32_TFLOPS,
-                     "packet_node_visits_per_64_rays": round(stats["wave_node_visits"] / (traced / 64), 1),
-                     "packet_gaussian_visits_per_64_rays": round(stats["wave_prim_visits"] / (traced / 64), 1)},
-    }
-    value = n * S / (ms_step * 1e-3) / 1e9
+    if args.million_only:
+        print(json.dumps({"ms_per_step": ms_step, "steps": args.steps}), flush=True)
+        return
     result = {
         "metric": "transfer precompute Grays/s + relit splats/s; BF16 vs FP32, fwd+bwd vs fwd",
-        "value": round(value, 4),
+        "value": round(n * S / (ms_step * 1e-3) / 1e9, 5),
         "unit": "Grays/s (nominal N*S rays per second of the whole step)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(ms_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "surface100k: unit sphere on a 4x4 plane, N=100,000, S=256, 16 SH coeffs, direct",
+        "config": {"workload": "million: unit sphere on a 4x4 plane (200,000 splats) + 20 ellipsoid shells x 40,000 "
+                               "splats, N=1,000,000, S=512, 16 SH coeffs x RGB, direct + 1 bounce",
                    "n_splats": n, "num_dirs": S, "sh_coeffs": params.K, "channels": params.channels,
                    "bounces": params.bounces},
-        "breakdown_ms": {"build_bvh": round(res["build"], 4), "transfer": round(res["transfer"], 4),
-                         "relight": round(res["relight"], 5)},
-        "traced_grays_per_s": round(rays_per_s / 1e9, 4),
-        "relit_splats_per_s": round(n / (res["relight"] * 1e-3), 1),
-        "traced_rays": traced,
-        "roofline": roofline,
     }
+    result.update(million_breakdown(prt, torch, np, sc, params, res, args.steps))
+    result["relit_splats_per_s"] = round(n / (res["relight"] * 1e-3), 1)
+    transfer_out, bvh = res["transfer_out"], res["bvh"]
     res.clear()
     torch.cuda.empty_cache()
     if not args.no_extras:
-        result["million_bounce"] = bench_million(prt, torch, scenegen, np)
-        result["relight_3m"] = bench_relight(prt, torch, scenegen, np, args.steps)
-        result["backward_200k"] = bench_backward(prt, torch, scenegen, np, args.steps)
-        result["glossy_100k"] = bench_glossy(prt, torch, scenegen, np, args.steps)
+        result["million_extras"] = bench_million_extras(prt, torch, scenegen, np, sc, bvh, params, light,
+                                                        transfer_out)
+        del transfer_out, bvh
+        torch.cuda.empty_cache()
+        result["surface100k_direct"] = bench_surface100k(prt, torch, scenegen, np, 20, 3)
+        result["relight_3m"] = bench_relight(prt, torch, scenegen, np, 20)
+        result["backward_200k"] = bench_backward(prt, torch, scenegen, np, 20)
+        result["glossy_100k"] = bench_glossy(prt, torch, scenegen, np, 20)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(arr, params, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+def roofline_of(kernel, stats, ms, bytes_per_unit, extra_unit_bytes=None, counters=None):
+    """Roofline of one traversal kernel: algorithmic bytes of the single-ray
+    work it performs per traced ray, times the rays of one launch, over the
+    measured launch time, against the HBM peak (the HBM-roofline-implied ray
+    throughput); beside it the DRAM traffic the counters measured and the
+    share of the VALU issue rate the kernel used."""
+    traced = stats["traced_rays"]
+    achieved = traced * bytes_per_unit / (ms * 1e-3) / 1e9
+    out = {
+        "kernel": kernel,
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / PEAK_HBM_GBS, 4),
+        "traffic": counters["bytes_per_launch"] if counters else None,
+        "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE, copy-calibrated)",
+        "what_frac_means": "traced rays/s over the HBM-roofline-implied ray rate 8 TB/s / algorithmic bytes per ray",
+        "units_per_launch": traced,
+        "unit_of_work": "traced ray",
+        "algorithmic_bytes_per_unit": round(bytes_per_unit, 1),
+        "ms_per_launch": round(ms, 3),
+    }
+    if extra_unit_bytes:
+        out["algorithmic_bytes_terms"] = extra_unit_bytes
+    if counters and counters.get("bytes_per_launch"):
+        out["measured_dram_GBps"] = round(counters["bytes_per_launch"] / (ms * 1e-3) / 1e9, 1)
+        out["measured_dram_frac"] = round(counters["bytes_per_launch"] / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+    if counters and counters.get("valu_instructions_per_launch"):
+        out["valu_issue_frac"] = round(counters["valu_instructions_per_launch"] / (VALU_WAVE_INSTR_PER_S * ms * 1e-3), 3)
+    return out
+
+
+def million_breakdown(prt, torch, np, sc, params, res, steps):
+    """Per-pass times of the headline step (HIP events on the library's
+    stream), the single-ray work of each pass, and the roofline of the bounce
+    walk, the dominant kernel."""
+    direct = prt.TransferParams(num_dirs=params.num_dirs, sh_bands=params.sh_bands, bounces=0)
+    out = torch.zeros((sc.n, 1, params.K), dtype=torch.float32, device="cuda")
+    ws = prt.Workspace()
+    prt.precompute_transfer(sc, res["bvh"], direct, out=out, workspace=ws)
+    times = []
+    for _ in range(max(3, min(steps, 5))):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        prt.precompute_transfer(sc, res["bvh"], direct, out=out, workspace=ws)
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    t_direct = float(np.median(times))
+    t_transfer = float(np.median(res["transfer_all"]))
+    t_bounce = t_transfer - t_direct
+    del out
+    sd = prt.traversal_stats(sc, res["bvh"], direct, workspace=ws)
+    del ws
+    torch.cuda.empty_cache()
+    sb = prt.traversal_stats(sc, res["bvh"], params)
+    torch.cuda.empty_cache()
+    K = params.K
+    td = sd["traced_rays"]
+    d_box, d_prim = sd["box_tests"] / td, sd["prim_tests"] / td
+    tb = sb["traced_rays"]
+    b_box, b_prim = sb["box_tests"] / tb, sb["prim_tests"] / tb
+    blended, listed, rounds = sb["blended_hits"] / tb, sb["listed_hits"] / tb, sb["rounds"] / tb
+    hit_bytes = 4 * K + 12
+    # direct: traversal + the ray's weight written and read back by the projection
+    b_direct = BYTES_PER_BOX_TEST * d_box + BYTES_PER_PRIM_TEST * d_prim
+    # bounce: its own (culled) traversal, the hits blended, the cut depth read
+    b_bounce = BYTES_PER_BOX_TEST * b_box + BYTES_PER_PRIM_TEST * b_prim + hit_bytes * blended + 4
+    log(f"million: direct {t_direct:.0f} ms ({d_box:.0f} box / {d_prim:.0f} Gaussian tests per ray), bounce "
+        f"{t_bounce:.0f} ms ({b_box:.0f} / {b_prim:.0f} per ray, {blended:.1f} blended / {listed:.1f} listed hits, "
+        f"{rounds:.3f} rounds)")
+    roof = roofline_of("bounce_kernel<16> (the blended bounce walk: culled traversal, nearest-first selection, blend; "
+                       "timed as the bounce call minus the direct call)",
+                       sb, t_bounce, b_bounce,
+                       {"box_tests": round(b_box, 2), "prim_tests": round(b_prim, 2),
+                        "blended_hits": round(blended, 2), "bytes_per_blended_hit": hit_bytes,
+                        "listed_hits": round(listed, 2), "rounds": round(rounds, 4), "cut_depth_bytes": 4},
+                       measured("bounce_million"))
+    direct_roof = roofline_of("direct_kernel + project_kernel (visibility traversal, then SH projection)", sd,
+                              t_direct, b_direct, {"box_tests": round(d_box, 2), "prim_tests": round(d_prim, 2)})
+    direct_roof["packet_node_visits_per_64_rays"] = round(sd["wave_node_visits"] / (td / 64), 1)
+    direct_roof["packet_gaussian_visits_per_64_rays"] = round(sd["wave_prim_visits"] / (td / 64), 1)
+    roof["packet_node_visits_per_64_rays"] = round(sb["wave_node_visits"] / (tb / 64), 1)
+    roof["packet_gaussian_visits_per_64_rays"] = round(sb["wave_prim_visits"] / (tb / 64), 1)
+    return {
+        "breakdown_ms": {"build_bvh": round(res["build"], 3), "direct_pass": round(t_direct, 2),
+                         "bounce_pass": round(t_bounce, 2), "relight": round(res["relight"], 4),
+                         "transfer_call": round(t_transfer, 2)},
+        "traced_rays": td,
+        "direct_traced_grays_per_s": round(td / (t_direct * 1e-3) / 1e9, 4),
+        "grays_per_s_without_build": round(sc.n * params.num_dirs / ((res["ms_step"] - res["build"]) * 1e-3) / 1e9,
+                                           5),
+        "roofline": roof,
+        "direct_roofline": direct_roof,
+    }
 
 
 def time_steps(prt, torch, np, sc, params, light, steps, warmup):
@@ -267,49 +355,56 @@ def time_steps(prt, torch, np, sc, params, light, steps, warmup):
     wall = time.perf_counter() - t0
     return {"ms_step": wall * 1e3 / steps, "build": float(np.mean(timer.ms("build"))),
             "transfer": float(np.mean(timer.ms("transfer"))), "relight": float(np.mean(timer.ms("relight"))),
-            "bvh": holder["bvh"], "transfer_out": transfer}
+            "transfer_all": timer.ms("transfer"), "bvh": holder["bvh"], "transfer_out": transfer}
 
 
-def bench_million(prt, torch, scenegen, np):
-    """1,000,000 splats, S=512, 16 coeffs, RGB with one bounce: one timed
-    step (build + direct + bounce + relight) after one warm-up step."""
-    log("million-splat workload with one bounce")
-    arr, sc, params, light = workload_setup(prt, torch, scenegen, "million")
-    res = time_steps(prt, torch, np, sc, params, light, 1, 1)
-    direct = prt.TransferParams(num_dirs=params.num_dirs, sh_bands=params.sh_bands, bounces=0)
-    out = torch.zeros((sc.n, 1, params.K), dtype=torch.float32, device="cuda")
-    ws = prt.Workspace()
-    prt.precompute_transfer(sc, res["bvh"], direct, out=out, workspace=ws)
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    prt.precompute_transfer(sc, res["bvh"], direct, out=out, workspace=ws)
-    b.record()
-    torch.cuda.synchronize()
-    t_direct = a.elapsed_time(b)
-    stats = prt.traversal_stats(sc, res["bvh"], direct)
+def bench_surface100k(prt, torch, scenegen, np, steps, warmup):
+    """The 100k-splat surface workload (S = 256, 16 coefficients, direct
+    transfer only): build + transfer + relight per step, and the roofline of
+    its traversal kernel."""
+    log("surface100k: direct transfer")
+    arr, sc, params, light = workload_setup(prt, torch, scenegen, "surface100k")
+    res = time_steps(prt, torch, np, sc, params, light, steps, warmup)
+    stats = prt.traversal_stats(sc, res["bvh"], params)
     traced = stats["traced_rays"]
     n_box, n_prim = stats["box_tests"] / traced, stats["prim_tests"] / traced
     b_ray = BYTES_PER_BOX_TEST * n_box + BYTES_PER_PRIM_TEST * n_prim
-    out_d = {"workload": "million: surface scene 200k + 20 shells x 40k, S=512, 16 coeffs, RGB + 1 bounce",
-             "ms_per_step": round(res["ms_step"], 2),
-             "nominal_grays_per_s": round(sc.n * params.num_dirs / (res["ms_step"] * 1e-3) / 1e9, 4),
-             "breakdown_ms": {"build_bvh": round(res["build"], 3), "direct_pass": round(t_direct, 2),
-                              "bounce_pass": round(res["transfer"] - t_direct, 2), "relight": round(res["relight"], 4)},
-             "direct_traced_grays_per_s": round(traced / (t_direct * 1e-3) / 1e9, 4),
-             "per_ray": {"box_tests": round(n_box, 2), "prim_tests": round(n_prim, 2),
-                         "algorithmic_bytes": round(b_ray, 1)},
-             "direct_hbm_implied_frac": round(traced / (t_direct * 1e-3) * b_ray / 1e9 / PEAK_HBM_GBS, 4)}
-    log(f"million: step {res['ms_step']:.0f} ms, direct {t_direct:.0f} ms")
-    # the paper's own bounce: index matrix once, then n bounces by gathers
+    f_ray = FLOPS_PER_BOX_TEST * n_box + FLOPS_PER_PRIM_TEST * n_prim
+    t_kernel = float(np.median(res["transfer_all"]))
+    roof = roofline_of("direct_kernel + project_kernel (visibility traversal, then SH projection; one call)", stats,
+                       t_kernel, b_ray, {"box_tests": round(n_box, 2), "prim_tests": round(n_prim, 2)},
+                       measured("direct_surface100k"))
+    roof["alu_view"] = {"algorithmic_flops_per_ray": round(f_ray, 1),
+                        "achieved_TFLOPs": round(traced / (t_kernel * 1e-3) * f_ray / 1e12, 3),
+                        "peak_TFLOPs": PEAK_FP32_TFLOPS,
+                        "packet_node_visits_per_64_rays": round(stats["wave_node_visits"] / (traced / 64), 1),
+                        "packet_gaussian_visits_per_64_rays": round(stats["wave_prim_visits"] / (traced / 64), 1)}
+    log(f"surface100k: step {res['ms_step']:.2f} ms, transfer {t_kernel:.2f} ms, frac {roof['frac']}")
+    out = {"workload": "surface100k: unit sphere on a 4x4 plane, N=100,000, S=256, 16 SH coeffs, direct",
+           "steps": steps, "ms_per_step": round(res["ms_step"], 3),
+           "nominal_grays_per_s": round(sc.n * params.num_dirs / (res["ms_step"] * 1e-3) / 1e9, 4),
+           "traced_grays_per_s": round(traced / (t_kernel * 1e-3) / 1e9, 4),
+           "breakdown_ms": {"build_bvh": round(res["build"], 4), "transfer": round(t_kernel, 4),
+                            "relight": round(res["relight"], 5)},
+           "roofline": roof}
+    del res
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_million_extras(prt, torch, scenegen, np, sc, bvh, params, light, transfer_out):
+    """On the million-splat scene: the paper's own bounce (index matrix, then
+    3 bounces by gathers), a relit 1080p frame, glossy matrices at S = 512."""
+    out_d = {}
     p_idx = prt.TransferParams(num_dirs=params.num_dirs, sh_bands=params.sh_bands, bounce_mode="index", bounces=3)
     out3 = torch.zeros((sc.n, 3, params.K), dtype=torch.float32, device="cuda")
     ws3 = prt.Workspace()
-    prt.precompute_transfer(sc, res["bvh"], p_idx, out=out3, workspace=ws3)
+    prt.precompute_transfer(sc, bvh, p_idx, out=out3, workspace=ws3)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     ev[0].record()
-    prt.precompute_transfer(sc, res["bvh"], p_idx, out=out3, workspace=ws3)
+    prt.precompute_transfer(sc, bvh, p_idx, out=out3, workspace=ws3)
     ev[1].record()
-    idx = prt.index_matrix(sc, res["bvh"], p_idx, workspace=ws3)
+    idx = prt.index_matrix(sc, bvh, p_idx, workspace=ws3)
     ev[2].record()
     prev = prt.self_transfer(sc, p_idx, idx, out3)
     ev[3].record()
@@ -327,11 +422,10 @@ def bench_million(prt, torch, scenegen, np):
     out_d["index_bounces"]["gather_GBps"] = round(g_bytes / (t_gather * 1e-3) / 1e9, 1)
     log(f"million index mode: direct + index + 3 bounces {t_all:.0f} ms, one gather bounce {t_gather:.2f} ms")
     del out3, ws3, idx, prev
-    out_d["frame_1080p"] = bench_frame(prt, torch, np, sc, res["transfer_out"], light)
-    del out
     torch.cuda.empty_cache()
-    out_d["glossy_1m"] = bench_glossy_million(prt, torch, scenegen, np, sc, res["bvh"], params)
-    del res
+    out_d["frame_1080p"] = bench_frame(prt, torch, np, sc, transfer_out, light)
+    torch.cuda.empty_cache()
+    out_d["glossy_1m"] = bench_glossy_million(prt, torch, scenegen, np, sc, bvh, params)
     torch.cuda.empty_cache()
     return out_d
 
@@ -580,34 +674,57 @@ def bench_backward(prt, torch, scenegen, np, steps):
 
 
 def cpu_baseline(arr, params, seconds):
-    """The oracle (brute force over all Gaussians per ray, FP64, all host
-    cores) on randomly sampled sources of the same workload, in batches until
-    the time budget is spent."""
+    """The oracle as it stands (brute force over all Gaussians per ray, FP64,
+    all host cores) on randomly sampled sources of the same workload, batch
+    by batch until the time budget is spent: each source's direct pass (every
+    traced ray tested against all N Gaussians) and, with a bounce, its bounce
+    walk (the same rays again, every hit listed, sorted and blended).  The
+    walk weighs the hit splats' direct transfers, which in the whole job come
+    from the direct pass already timed here; for timing alone it is given a
+    table of ones (the brute-force cost does not depend on the values)."""
     import numpy as np
 
     import oracle
     oracle.build()
     scene = {k: v.astype(np.float64) for k, v in arr.items()}
     n = scene["means"].shape[0]
+    S, bands = params.num_dirs, params.sh_bands
     threads = oracle.default_threads()
+    dirs = oracle.directions(S)
+    ones = np.ones((n, bands * bands)) if params.bounces else None
+    every = np.arange(n)
     rng = np.random.default_rng(7)
     log(f"cpu baseline: oracle, {threads} threads, ~{seconds:.0f} s")
-    done = 0
-    t0 = time.perf_counter()
+    done = traced = 0
+    t_direct = t_bounce = 0.0
     batch = max(threads, 16)
+    t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
         src = rng.choice(n, batch, replace=False)
-        oracle.direct_transfer(scene, params.num_dirs, params.sh_bands, sources=src, margins=None, threads=threads)
+        a = time.perf_counter()
+        oracle.direct_transfer(scene, S, bands, sources=src, margins=None, threads=threads)
+        b = time.perf_counter()
+        if params.bounces:
+            oracle.bounce_transfer(scene, S, bands, ones, every, sources=src, threads=threads)
+        c = time.perf_counter()
+        t_direct += b - a
+        t_bounce += c - b
         done += batch
-    elapsed = time.perf_counter() - t0
-    value = done * params.num_dirs / elapsed / 1e9
+        traced += int((scene["normals"][src] @ dirs.T > 0.0).sum())
+    elapsed = t_direct + t_bounce
+    value = done * S / elapsed / 1e9
     try:
         model = [ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")][0]
     except (OSError, IndexError):
         model = "unknown"
+    passes = 2 if params.bounces else 1
+    what = "direct pass + bounce walk" if params.bounces else "direct pass"
     return {"value": value, "unit": "Grays/s (nominal N*S rays per second)", "cores": threads, "kind": "oracle",
-            "sample": f"{done} random sources of the 100k surface workload ({done * params.num_dirs} nominal rays, "
-                      f"{elapsed:.1f} s), each traced ray tested against all {n} Gaussians, FP64",
+            "sample": f"{done} random sources of the {n}-splat workload ({done * S} nominal rays, {traced} traced, "
+                      f"{what}: {t_direct:.1f} s + {t_bounce:.1f} s), each traced ray tested against all {n} "
+                      f"Gaussians per pass, FP64",
+            "ray_gaussian_tests_per_s": round(passes * traced * (n - 1) / elapsed, 1),
+            "direct_pass_traced_rays_per_s": round(traced / t_direct, 1),
             "cpu_model": model}
 
 

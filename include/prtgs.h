@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PRTGS_ABI_VERSION 3   /* 3: splatting and glossy entry points */
+#define PRTGS_ABI_VERSION 4   /* 4: explicit work split in prtgs_transfer_desc */
 
 typedef enum {
     PRTGS_OK = 0,
@@ -53,6 +53,8 @@ typedef enum { PRTGS_F32 = 0, PRTGS_BF16 = 1, PRTGS_F16 = 2 } prtgs_dtype;
 #define PRTGS_FLAG_STACK_OVERFLOW 0x2u  /* BVH deeper than the traversal stack */
 #define PRTGS_FLAG_BAD_TREE 0x4u        /* malformed BVH (wrong buffer or n): traversal stopped */
 #define PRTGS_FLAG_BAD_INDEX 0x8u       /* an index-matrix entry outside [-1, n): skipped */
+#define PRTGS_FLAG_ROUND_CAP 0x10u      /* a bounce ray needed more than PRTGS_BOUNCE_MAX_ROUNDS
+                                           traversals; its walk stopped there */
 
 /* The splats (Sec. 3.1, Eq. 1-2; normal Sec. 4.3; albedo Sec. 4.2).
  * Caller-owned, read-only during calls. */
@@ -85,7 +87,19 @@ typedef struct {
     int32_t bounce_mode;       /* PRTGS_BOUNCE_BLEND or PRTGS_BOUNCE_INDEX */
     float t_same;              /* index mode: hits with transmittance in front above it are not
                                   candidates (same-surface filter); (0, 1], 1 = off */
+    /* Work split (0 = chosen by the library from the number of sources).  It
+     * changes only the order in which each ray's factors (1 - alpha) are
+     * multiplied and, for the blended bounce, how the per-direction sums are
+     * grouped before they are added: the last bits of the result. */
+    int32_t sources_per_wave;  /* sources traced together by one wave: 1 (one source per wave, its
+                                  hemisphere directions compacted), 2, 4, 8, 16, 32 or 64 */
+    int32_t direction_parts;   /* waves that share one source group's directions, 1 .. 64; the
+                                  blended bounce keeps at most PRTGS_BLEND_PARTS_MAX of them */
 } prtgs_transfer_desc;
+
+#define PRTGS_BLEND_PARTS_MAX 8     /* blended bounce: direction parts with sums of their own */
+#define PRTGS_BOUNCE_HIT_LIST 256   /* bounce walk: hits a ray lists per traversal round */
+#define PRTGS_BOUNCE_MAX_ROUNDS 4096 /* bounce walk: traversal rounds per ray (each blends >= 1 hit) */
 
 /* How a bounce weighs the hits of a ray.
  * BLEND: every hit front to back with weight alpha_j T_j (depth-ordered alpha
@@ -270,13 +284,19 @@ prtgs_status prtgs_glossy_transfer(const prtgs_gaussians* g /* host */, const fl
 prtgs_status prtgs_glossy_view(int32_t n, int32_t K, const float* matrices, const float* means,
                                const float* eye /* host */, float* transfer, hipStream_t stream);
 
-/* Work statistics of the direct pass over the selected sources (nothing else
- * is written): stats[0] traced rays, stats[1] child-box tests and stats[2]
- * Gaussian tests that a single-ray depth-first traversal of this BVH (same
- * child order, same early termination) performs, summed over rays;
+/* Work statistics (nothing else is written).  Direct pass (bounces == 0),
+ * over the selected sources: stats[0] traced rays, stats[1] child-box tests
+ * and stats[2] Gaussian tests that a single-ray depth-first traversal of this
+ * BVH (same child order, same early termination) performs, summed over rays;
  * stats[3] node visits and stats[4] Gaussian-record visits of the wave
- * packets, summed.  stats: device array of 8 uint64, overwritten.  ws as for
- * prtgs_precompute_transfer with bounces = 0. */
+ * packets, summed.  Blended bounce (bounces == 1, PRTGS_BOUNCE_BLEND; every
+ * source): the direct pass runs, then the bounce walk is counted the same way
+ * (stats[0] its traced rays, [1]-[4] its traversal work over every round and
+ * the depth intervals it walks), with stats[5] the hits blended (those with
+ * transmittance >= T_eps in front: the contributing hits), stats[6] the hits
+ * listed and stats[7] the traversal rounds, each summed over rays.  stats:
+ * device array of 8 uint64, overwritten.  ws as for prtgs_precompute_transfer
+ * with the same d.  Index mode: PRTGS_ERR_UNSUPPORTED. */
 prtgs_status prtgs_traversal_stats(const prtgs_gaussians* g /* host */, const void* bvh,
                                    const prtgs_transfer_desc* d /* host */, int32_t first, int32_t count,
                                    uint64_t* stats, void* ws, size_t ws_bytes, hipStream_t stream);

@@ -93,6 +93,8 @@ class TransferParams:
     alpha_max: float = 0.99
     bounce_mode: str = "blend"     # "blend" (depth-ordered alpha blend, 1 bounce) or "index" (argmax, n bounces)
     t_same: float = 1.0            # index mode: same-surface filter (1 = off)
+    sources_per_wave: int = 0      # work split (0 = the library's choice); changes only the last bits
+    direction_parts: int = 0
 
     @property
     def K(self) -> int:
@@ -105,7 +107,8 @@ class TransferParams:
     def c_struct(self) -> _lib.TransferDesc:
         mode = {"blend": _lib.BOUNCE_BLEND, "index": _lib.BOUNCE_INDEX}[self.bounce_mode]
         return _lib.TransferDesc(self.num_dirs, self.sh_bands, self.seed, self.bounces, self.sigma_cut, self.t_min,
-                                 self.T_eps, self.alpha_min, self.alpha_max, mode, self.t_same)
+                                 self.T_eps, self.alpha_min, self.alpha_max, mode, self.t_same,
+                                 self.sources_per_wave, self.direction_parts)
 
     def cut(self) -> dict:
         return dict(sigma_cut=self.sigma_cut, t_min=self.t_min, T_eps=self.T_eps, alpha_min=self.alpha_min,
@@ -139,6 +142,8 @@ def check_flags(ws: torch.Tensor, what: str = "kernel"):
         raise RuntimeError(f"{what}: malformed BVH (buffer built for another scene?)")
     if f & _lib.FLAG_BAD_INDEX:
         raise IndexError(f"{what}: an index-matrix entry lies outside [-1, n)")
+    if f & _lib.FLAG_ROUND_CAP:
+        raise RuntimeError(f"{what}: a bounce ray needed more traversal rounds than the library allows")
 
 
 # ----------------------------------------------------------------------------
@@ -376,20 +381,24 @@ def splat_render(scene: Scene, colours: torch.Tensor, cam, max_instances: int | 
 
 def traversal_stats(scene: Scene, bvh: Bvh, params: TransferParams, first: int = 0, count: int | None = None,
                     workspace: Workspace | None = None) -> dict:
-    """Single-ray work counts of the direct pass (see prtgs_traversal_stats)."""
+    """Single-ray work counts of the direct pass, or with ``params.bounces``
+    (blend) of the bounce walk (see prtgs_traversal_stats)."""
     lib = _lib.load()
     n = scene.n
     count = n - first if count is None else count
     g = scene.c_struct()
     d = params.c_struct()
-    d.bounces = 0
     wbytes = lib.prtgs_transfer_workspace_bytes(ctypes.byref(d), n)
     ws = (workspace or Workspace()).get(wbytes, scene.device)
     stats = torch.zeros(8, dtype=torch.int64, device=scene.device)
     _lib.check(lib.prtgs_traversal_stats(ctypes.byref(g), _ptr(bvh.buffer), ctypes.byref(d), first, count, _ptr(stats),
                                          _ptr(ws), ws.numel(), _stream()))
     v = stats.cpu().tolist()
-    return dict(traced_rays=v[0], box_tests=v[1], prim_tests=v[2], wave_node_visits=v[3], wave_prim_visits=v[4])
+    check_flags(ws, "traversal_stats")
+    out = dict(traced_rays=v[0], box_tests=v[1], prim_tests=v[2], wave_node_visits=v[3], wave_prim_visits=v[4])
+    if params.bounces:
+        out.update(blended_hits=v[5], listed_hits=v[6], rounds=v[7])
+    return out
 
 
 def pack(x: torch.Tensor, dtype: str) -> torch.Tensor:

@@ -260,7 +260,7 @@ template <int K>
 hipError_t launch_bwd_k(const BackwardArgs& a, hipStream_t stream)
 {
     BackwardArgs b = a;
-    b.fwd.Q = direction_parts(a.fwd.G, a.fwd.S);
+    b.fwd.Q = direction_parts(a.fwd.G, a.fwd.S, a.fwd.Q_req);
     const int64_t waves = (int64_t)((a.fwd.count + a.fwd.G - 1) / a.fwd.G) * b.fwd.Q;
     const int blocks = (int)((waves + kBlock / kWave - 1) / (kBlock / kWave));
     hipLaunchKernelGGL(transfer_backward_kernel<K>, dim3(blocks), dim3(kBlock), 0, stream, b);

@@ -73,6 +73,11 @@ prtgs_status check_desc(const prtgs_transfer_desc* d)
         return fail(PRTGS_ERR_INVALID_ARG, "alpha_max outside (0, 0.999]");
     if (!(d->alpha_min >= 0.0f && d->alpha_min <= d->alpha_max))
         return fail(PRTGS_ERR_INVALID_ARG, "alpha_min outside [0, alpha_max]");
+    const int g = d->sources_per_wave;
+    if (g != 0 && g != 1 && g != 2 && g != 4 && g != 8 && g != 16 && g != 32 && g != 64)
+        return fail(PRTGS_ERR_INVALID_ARG, "sources_per_wave = %d not 0 or a power of two up to 64", g);
+    if (d->direction_parts < 0 || d->direction_parts > 64)
+        return fail(PRTGS_ERR_INVALID_ARG, "direction_parts = %d outside [0, 64]", d->direction_parts);
     return PRTGS_OK;
 }
 
@@ -124,18 +129,15 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
 
 // Sources per wave of the group split; 1 selects the fan kernel.  With the
 // direction batches spread over waves a launch holds ~count S / 64 waves
-// whatever G is, so G is chosen by measurement (S = 256 surface scenes):
-// 16 from 40k sources (50k: 6.2 ms against 6.7 for G = 8; 100k: 16.9 against
-// 19.5), 8 from 10k (20k: 1.9 against 2.0 for 16, 2.9 for 2), 4 from 2048
-// (5k: 0.61 against 0.89 for the fan kernel), the fan kernel below.
-int group_size(int count)
+// whatever G is, so the default is chosen by measurement (S = 256 surface
+// scenes): 16 from 40k sources (50k: 6.2 ms against 6.7 for G = 8; 100k: 16.9
+// against 19.5), 8 from 10k (20k: 1.9 against 2.0 for 16, 2.9 for 2), 4 from
+// 2048 (5k: 0.61 against 0.89 for the fan kernel), the fan kernel below.
+// `requested` (a power of two up to 64, 0 = this default) is the caller's.
+int group_size(int count, int requested)
 {
-    int G = count >= 40000 ? 16 : count >= 10000 ? 8 : count >= 2048 ? 4 : 1;
-    if (const char* env = getenv("PRTGS_GROUP")) {
-        int g = atoi(env);
-        if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64) G = g;
-    }
-    return G;
+    if (requested > 0) return requested;
+    return count >= 40000 ? 16 : count >= 10000 ? 8 : count >= 2048 ? 4 : 1;
 }
 
 HitParams hit_params(const prtgs_transfer_desc& d)
@@ -259,7 +261,8 @@ TransferArgs transfer_args(const prtgs_gaussians* g, const void* bvh, const prtg
     a.partial = bounce && d->bounce_mode == PRTGS_BOUNCE_BLEND ? reinterpret_cast<float*>(w + W.partial) : nullptr;
     a.index = nullptr;
     a.t_same = d->t_same;
-    a.G = group_size(count);
+    a.G = group_size(count, d->sources_per_wave);
+    a.Q_req = d->direction_parts;
     a.flags = reinterpret_cast<unsigned*>(w);
     return a;
 }
@@ -567,55 +570,33 @@ prtgs_status prtgs_traversal_stats(const prtgs_gaussians* g, const void* bvh, co
 {
     prtgs_status st = check_desc(d);
     if (st != PRTGS_OK) return st;
-    st = check_gaussians(g, false);
+    const bool bounce = d->bounces > 0;
+    if (bounce && d->bounce_mode != PRTGS_BOUNCE_BLEND)
+        return fail(PRTGS_ERR_UNSUPPORTED, "work statistics cover the direct pass and the blended bounce");
+    st = check_gaussians(g, bounce);
     if (st != PRTGS_OK) return st;
     const int n = g->n;
     if (!bvh || !ws || !stats) return fail(PRTGS_ERR_INVALID_ARG, "bvh, workspace or stats is NULL");
     if (!aligned256(bvh) || !aligned256(ws)) return fail(PRTGS_ERR_INVALID_ARG, "bvh and workspace must be 256-byte aligned");
     if (first < 0 || count < 0 || (int64_t)first + count > n)
         return fail(PRTGS_ERR_INVALID_ARG, "source range [%d, %d + %d) outside [0, %d)", first, first, count, n);
-    prtgs_transfer_desc dd = *d;
-    dd.bounces = 0;
-    TransferWs W = transfer_ws_layout(dd, n);
+    if (bounce && (first != 0 || count != n))
+        return fail(PRTGS_ERR_INVALID_ARG, "a bounce needs every source's direct transfer: use first = 0, count = n");
+    TransferWs W = transfer_ws_layout(*d, n);
     if (ws_bytes < W.total)
         return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes, W.total);
     char* w = static_cast<char*>(ws);
-    unsigned* flags = reinterpret_cast<unsigned*>(w);
-    float* dirs = reinterpret_cast<float*>(w + W.dirs);
-    float* Y = reinterpret_cast<float*>(w + W.Y);
-    hipError_t e = fill_u32(flags, 0u, 1, stream);
+    hipError_t e = transfer_setup(d, w, W, stream);
     if (e == hipSuccess) e = fill_u32(reinterpret_cast<uint32_t*>(stats), 0u, 16, stream);
-    if (e == hipSuccess)
-        e = launch_direction_table(d->num_dirs, d->seed, d->sh_bands, nullptr, nullptr, dirs, Y, stream);
-    if (e == hipSuccess) e = launch_direction_order(d->num_dirs, reinterpret_cast<int32_t*>(w + W.dir_order), stream);
     if (e != hipSuccess) return hip_status(e, "traversal stats setup");
     if (count == 0) return ok();
-    const BvhLayout L = bvh_layout(n);
-    const char* b = static_cast<const char*>(bvh);
-    TransferArgs a{};
-    a.nodes = reinterpret_cast<const Node*>(b + L.nodes);
-    a.prims = reinterpret_cast<const Prim*>(b + L.prims);
-    a.normals = reinterpret_cast<const float4*>(b + L.normals);
-    a.order = reinterpret_cast<const int32_t*>(b + L.order);
-    a.dirs = dirs;
-    a.Y = Y;
-    a.dir_order = reinterpret_cast<const int32_t*>(w + W.dir_order);
-    a.S = d->num_dirs;
-    a.K = d->sh_bands * d->sh_bands;
-    a.n = n;
-    a.first = first;
-    a.count = count;
-    a.channels = 1;
-    a.hp = hit_params(*d);
-    a.transfer = nullptr;
-    a.vis = nullptr;
-    a.tdir_sorted = nullptr;
-    a.albedo = nullptr;
-    a.albedo_sorted = nullptr;
-    a.G = group_size(count);
-    a.flags = flags;
-    return hip_status(launch_transfer_direct(a, stream, reinterpret_cast<unsigned long long*>(stats)),
-                      "traversal stats");
+    TransferArgs a = transfer_args(g, bvh, d, first, count, nullptr, nullptr, w, W);
+    unsigned long long* st64 = reinterpret_cast<unsigned long long*>(stats);
+    if (!bounce) return hip_status(launch_transfer_direct(a, stream, st64), "traversal stats");
+    // the direct pass (its transfers and cut depths feed the walk), then the counted walk
+    e = launch_transfer_direct(a, stream);
+    if (e == hipSuccess) e = launch_bounce_stats(a, stream, st64);
+    return hip_status(e, "traversal stats");
 }
 
 prtgs_status prtgs_pack(int64_t count, const float* src, void* dst, prtgs_dtype dtype, hipStream_t stream)
@@ -726,7 +707,8 @@ prtgs_status prtgs_transfer_backward(const prtgs_gaussians* g, const void* bvh, 
     a.fwd.tdir_sorted = nullptr;
     a.fwd.albedo = nullptr;
     a.fwd.albedo_sorted = nullptr;
-    a.fwd.G = group_size(n);
+    a.fwd.G = group_size(n, d->sources_per_wave);
+    a.fwd.Q_req = d->direction_parts;
     a.fwd.flags = flags;
     a.d_transfer = d_transfer;
     a.vis_in = vis;

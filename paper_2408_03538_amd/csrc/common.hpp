@@ -2,7 +2,6 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
-#include <stdlib.h>
 
 #include <algorithm>
 #include <stddef.h>
@@ -15,10 +14,11 @@ namespace prtgs {
 constexpr int kWave = 64;                 // CDNA wavefront width
 constexpr float kBoxSigma = 3.0f;         // BVH boxes enclose the 3-sigma ellipsoid
 constexpr size_t kFlagBytes = 256;        // flag word + padding at the head of a workspace
-constexpr int kHitList = 256;             // bounce: hits listed per ray and round
+constexpr int kHitList = PRTGS_BOUNCE_HIT_LIST;   // bounce: hits listed per ray and round
 constexpr int kBounceWavesPerSimd = 4;    // bounce (blend): resident waves per SIMD
 constexpr int kIndexWavesPerSimd = 5;     // bounce (index matrix): resident waves per SIMD
-constexpr int kBlendPartsMax = 8;         // bounce (blend): direction parts with sums of their own
+constexpr int kBlendPartsMax = PRTGS_BLEND_PARTS_MAX;   // bounce (blend): direction parts with sums of their own
+constexpr int kMaxRounds = PRTGS_BOUNCE_MAX_ROUNDS;     // bounce: traversal rounds per ray
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -165,11 +165,14 @@ struct TransferArgs {
     int G;                  // sources per wave (group split); 1 = fan kernel
     int Q;                  // group split: waves per source group, each taking a
                             // contiguous share of the direction batches (part-major)
+    int Q_req;              // the caller's direction parts (0 = the default)
     unsigned* flags;
 };
 hipError_t launch_transfer_direct(const TransferArgs& a, hipStream_t stream, unsigned long long* stats = nullptr);
 hipError_t launch_transfer_bounce(const TransferArgs& a, hipStream_t stream);
 hipError_t launch_transfer_index(const TransferArgs& a, hipStream_t stream);
+// the blended bounce's walk with its work tallied into stats[8] (no transfer written)
+hipError_t launch_bounce_stats(const TransferArgs& a, hipStream_t stream, unsigned long long* stats);
 hipError_t launch_self_transfer(int n, int S, int K, const float* dirs, const float* normals, const float* albedo,
                                 const int32_t* index, const float* t_prev, int c_prev, float* t_out, unsigned* flags,
                                 hipStream_t stream);
@@ -184,16 +187,13 @@ hipError_t launch_add(float* acc, const float* x, size_t count, hipStream_t stre
 // horizon.  Measured at 100k x 256 (8 sources per wave): Q = 1, 4, 8, 32
 // give 31.8, 23.4, 21.1, 19.4 ms; with 16 sources per wave Q = 16, 32, 64
 // give 18.1, 16.9, 16.3 ms; at 1M x 512 Q = 1, 8, 32, 128: 1021, 935, 934,
-// 938 ms.  One batch per wave, at most 64 parts.
-inline int direction_parts(int G, int S)
+// 938 ms.  One batch per wave, at most 64 parts.  `requested` (1 .. 64, 0 =
+// this default) is the caller's choice, capped at the number of batches.
+inline int direction_parts(int G, int S, int requested)
 {
     const int batches = (S + kWave / G - 1) / (kWave / G);
-    int Q = std::min(batches, 64);
-    if (const char* env = getenv("PRTGS_DPARTS")) {
-        const int q = atoi(env);
-        if (q >= 1 && q <= batches) Q = q;
-    }
-    return std::max(Q, 1);
+    int Q = requested > 0 ? requested : 64;
+    return std::max(std::min(Q, batches), 1);
 }
 
 // Persistent waves of the bounce launch for n sources (any group size): as

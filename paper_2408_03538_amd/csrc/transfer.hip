@@ -153,18 +153,38 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 
 // The SH projection of the direct pass (Eq. 29 over the S directions):
 // one thread per source sums rayw[pos] Y(w_s) over the direction-order
-// positions in FP64 (loads of 8 positions in flight; the direction's Y row is
-// uniform across the wave and comes through the scalar unit), then writes the
+// positions (loads of 8 positions in flight; the direction's Y row is uniform
+// across the wave and comes through the scalar unit), then writes the
 // transfer (copied to every channel) and, for a bounce, the leaf-order copies.
+// The sums are compensated FP32 dot products (Ogita, Rump and Oishi's Dot2):
+// each product's rounding error comes from an FMA and each addition's from
+// Neumaier's branch-free TwoSum variant, both carried in a second float, so
+// the result is as if summed in about twice the precision and then rounded.
+// The order is fixed (direction order), so the transfer is the same for
+// every work split.
+__device__ inline void dot2_add(float w, float y, float& sum, float& comp)
+{
+#pragma clang fp contract(off)   // p and t must be the rounded product and sum
+    const float p = w * y;
+    const float pe = fmaf(w, y, -p);          // w y - p exactly
+    const float t = sum + p;
+    const float se = fabsf(sum) >= fabsf(p) ? (sum - t) + p : (p - t) + sum;   // sum + p - t exactly
+    sum = t;
+    comp += pe + se;
+}
+
 template <int K>
 __global__ __launch_bounds__(kBlock) void project_kernel(TransferArgs a)
 {
     const int local = blockIdx.x * kBlock + threadIdx.x;
     if (local >= a.count) return;
     const int rank = a.first + local;
-    double acc[K];
+    float acc[K], cmp[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int k = 0; k < K; ++k) {
+        acc[k] = 0.0f;
+        cmp[k] = 0.0f;
+    }
     constexpr int kAhead = 8;
     int pos = 0;
     for (; pos + kAhead <= a.S; pos += kAhead) {
@@ -175,21 +195,21 @@ __global__ __launch_bounds__(kBlock) void project_kernel(TransferArgs a)
         for (int u = 0; u < kAhead; ++u) {
             const float* y = a.Y + (size_t)a.dir_order[pos + u] * K;
 #pragma unroll
-            for (int k = 0; k < K; ++k) acc[k] = fma((double)w[u], (double)y[k], acc[k]);
+            for (int k = 0; k < K; ++k) dot2_add(w[u], y[k], acc[k], cmp[k]);
         }
     }
     for (; pos < a.S; ++pos) {
         const float w = a.rayw[(size_t)pos * a.count + local];
         const float* y = a.Y + (size_t)a.dir_order[pos] * K;
 #pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] = fma((double)w, (double)y[k], acc[k]);
+        for (int k = 0; k < K; ++k) dot2_add(w, y[k], acc[k], cmp[k]);
     }
-    const double scale = 4.0 * 3.14159265358979323846 / (double)a.S;
+    const float scale = kFourPi / (float)a.S;
     float t[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) t[k] = (float)(acc[k] * scale);
+    for (int k = 0; k < K; ++k) t[k] = (acc[k] + cmp[k]) * scale;
     const int orig = a.order[rank];
-    for (int ch = 0; ch < a.channels; ++ch) {
+    for (int ch = 0; a.transfer && ch < a.channels; ++ch) {
         float* out = a.transfer + ((size_t)orig * a.channels + ch) * K;
 #pragma unroll
         for (int k = 0; k < K; ++k) out[k] = t[k];
@@ -363,8 +383,10 @@ __device__ inline void merge_chunk(uint64_t (&kk)[N], float (&aa)[N], uint64_t (
 // hits with T_j <= t_same (the nearer one on equal weights) in the index
 // matrix (-1: none, or not traced), and nothing is accumulated.  kScan list
 // entries are loaded together in the selection.
-template <int K, bool kIndex, int kScan>
-__device__ __forceinline__ void bounce_walk(const TransferArgs& a)
+// kCount (blend only): the walk also tallies its work into stats (see
+// launch_bounce_stats); the results are the same.
+template <int K, bool kIndex, int kScan, bool kCount = false>
+__device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long long* stats = nullptr)
 {
     constexpr int M = kHitList;
     const int lane = threadIdx.x & (kWave - 1);
@@ -379,8 +401,8 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a)
     int2* const lrec = kIndex ? nullptr : a.hitrec + (size_t)wslot * M * kWave + lane;
     const int groups = (a.count + G - 1) / G;
     const HitParams hp = a.hp;
-    // Each traversal blends at least one of at most n - 1 hits, hence the cap.
-    const int max_rounds = a.n + 1;
+    RayCounts rc;   // (kCount) single-ray traversal work, hits blended and listed, rounds
+    uint32_t n_traced = 0, n_blended = 0, n_listed = 0, n_rounds = 0;
 
     for (;;) {
         // items are (direction part, source group), taken part-major as in the
@@ -412,6 +434,7 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a)
             if (kIndex && valid && inrange && !pending) a.index[(size_t)orig * a.S + s] = -1;
             if (__ballot(pending) == 0ull) continue;
             const bool traced = pending;
+            if (kCount && traced) ++n_traced;
             const BatchDir bd = batch_dir(d, pending);
             const float wc = c * kInvPi;
             // No hit beyond tc can carry weight: the direct pass saw the
@@ -424,13 +447,20 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a)
             uint64_t k_last = 0;   // key of the last blended hit (once started)
             int rounds = 0;
             while (__ballot(pending) != 0ull) {
-                // a traversal that ran out of its budget flagged the tree: stop
-                if (pending && (++rounds > max_rounds ||
-                                (__atomic_load_n(a.flags, __ATOMIC_RELAXED) & PRTGS_FLAG_BAD_TREE))) {
-                    raise_flag(a.flags, PRTGS_FLAG_BAD_TREE);
+                // A traversal that ran out of its budget flagged the tree: stop.
+                // Every round blends at least one listed hit (compact keeps the
+                // nearest), so a ray ends within as many rounds as it has hits;
+                // the cap bounds the work of a pathological scene.
+                if (pending && (__atomic_load_n(a.flags, __ATOMIC_RELAXED) & PRTGS_FLAG_BAD_TREE)) {
                     pending = false;
                     continue;
                 }
+                if (pending && ++rounds > kMaxRounds) {
+                    raise_flag(a.flags, PRTGS_FLAG_ROUND_CAP);
+                    pending = false;
+                    continue;
+                }
+                if (kCount && pending) ++n_rounds;
                 int cnt = 0;
                 float sum_t = 0.0f;         // of the listed hits (compaction pivot)
                 uint64_t k_over = kNoHit;   // hits from here on wait for the next round
@@ -445,10 +475,19 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a)
                 float P[kCheck];
 #pragma unroll
                 for (int b = 0; b < kCheck; ++b) P[b] = T;
-                // Full list: keep the hits in front of their mean depth (at least
-                // one goes: if rounding keeps them all, the farthest).
+                // Full list: keep the hits in front of their mean depth.  At
+                // least one goes (if rounding keeps them all, the farthest) and
+                // at least one stays (the nearest, also when every listed depth
+                // is the same and the mean rounds to it or below), so the round
+                // blends a hit and the next one starts beyond it.
                 auto compact = [&]() {
-                    const uint64_t pivot = hit_key(sum_t / (float)cnt, 0);
+                    uint64_t kmin = kNoHit;   // every listed key is below k_over
+                    for (int q = 0; q < cnt; ++q) {
+                        const uint64_t k = lkey[q * kWave];
+                        kmin = k < kmin ? k : kmin;
+                    }
+                    uint64_t pivot = hit_key(sum_t / (float)cnt, 0);
+                    pivot = pivot > kmin ? pivot : kmin + 1;
                     if (pivot < k_over) k_over = pivot;
                     int kept = 0;
                     float kept_sum = 0.0f;
@@ -508,7 +547,8 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a)
                         }
                     }
                 };
-                traverse_batch<false>(a, d, bd, ox, oy, oz, live, tlo, thi, leaf, (RayCounts*)nullptr);
+                traverse_batch<kCount>(a, d, bd, ox, oy, oz, live, tlo, thi, leaf, kCount ? &rc : (RayCounts*)nullptr);
+                if (kCount && pending) n_listed += cnt;
 
                 int maxcnt = pending ? cnt : 0;
                 for (int off = 32; off >= 1; off >>= 1) maxcnt = max(maxcnt, __shfl_xor(maxcnt, off, kWave));
@@ -583,6 +623,7 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a)
                     // a buffer that came back short held the last listed hits
                     if (done || got < kBlend) more = false;
                 }
+                if (kCount) n_blended += nrec;
                 // a list that overflowed and is still transparent: traverse on
                 if (done || k_over == kNoHit) pending = false;
                 // Sum the round's blended hits in blend order and add them to
@@ -638,6 +679,18 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a)
             if (kIndex && traced) a.index[(size_t)orig * a.S + s] = bestr >= 0 ? a.order[bestr] : -1;
         }
     }
+    if constexpr (kCount) {
+        atomicAdd(&stats[0], (unsigned long long)n_traced);
+        atomicAdd(&stats[1], (unsigned long long)rc.box_tests);
+        atomicAdd(&stats[2], (unsigned long long)rc.prim_tests);
+        if (lane == 0) {
+            atomicAdd(&stats[3], (unsigned long long)rc.wave_nodes);
+            atomicAdd(&stats[4], (unsigned long long)rc.wave_leaves);
+        }
+        atomicAdd(&stats[5], (unsigned long long)n_blended);
+        atomicAdd(&stats[6], (unsigned long long)n_listed);
+        atomicAdd(&stats[7], (unsigned long long)n_rounds);
+    }
 }
 
 // The two modes hold different registers at their peak (the blend its 3K
@@ -655,6 +708,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kIndexWa
     TransferArgs a)
 {
     bounce_walk<K, true, 4>(a);
+}
+// the blend's walk with its work tallied (prtgs_traversal_stats)
+template <int K>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceWavesPerSimd))) void bounce_count_kernel(
+    TransferArgs a, unsigned long long* stats)
+{
+    bounce_walk<K, false, 8, true>(a, stats);
 }
 
 // ---------------------------------------------------------------------------
@@ -737,7 +797,7 @@ template <int K>
 hipError_t launch_direct_k(const TransferArgs& a, unsigned long long* stats, hipStream_t stream)
 {
     TransferArgs b = a;
-    b.Q = a.G == 1 ? 1 : direction_parts(a.G, a.S);
+    b.Q = a.G == 1 ? 1 : direction_parts(a.G, a.S, a.Q_req);
     if (stats) {
         hipLaunchKernelGGL((direct_kernel<true>), dim3(group_blocks(a.count, a.G, b.Q)), dim3(kBlock), 0, stream, b,
                            stats);
@@ -755,12 +815,12 @@ hipError_t launch_direct_k(const TransferArgs& a, unsigned long long* stats, hip
 }
 
 template <int K, bool kIndex>
-hipError_t launch_bounce_k(const TransferArgs& a, hipStream_t stream)
+hipError_t launch_bounce_k(const TransferArgs& a, hipStream_t stream, unsigned long long* stats = nullptr)
 {
     hipError_t e = fill_u32(a.queue, 0u, 1, stream);
     if (e != hipSuccess) return e;
     TransferArgs b = a;
-    b.Q = direction_parts(a.G, a.S);
+    b.Q = direction_parts(a.G, a.S, a.Q_req);
     if constexpr (!kIndex) {
         // the blend keeps a set of sums per part: at most kBlendPartsMax parts
         b.Q = std::min(b.Q, kBlendPartsMax);
@@ -773,6 +833,8 @@ hipError_t launch_bounce_k(const TransferArgs& a, hipStream_t stream)
     const dim3 grid((waves + kBlock / kWave - 1) / (kBlock / kWave));
     if constexpr (kIndex) {
         hipLaunchKernelGGL(index_kernel<K>, grid, dim3(kBlock), 0, stream, b);
+    } else if (stats) {
+        hipLaunchKernelGGL(bounce_count_kernel<K>, grid, dim3(kBlock), 0, stream, b, stats);
     } else {
         hipLaunchKernelGGL(bounce_kernel<K>, grid, dim3(kBlock), 0, stream, b);
         e = hipGetLastError();
@@ -806,6 +868,18 @@ hipError_t launch_transfer_bounce(const TransferArgs& a, hipStream_t stream)
         case 4: return launch_bounce_k<4, false>(a, stream);
         case 9: return launch_bounce_k<9, false>(a, stream);
         case 16: return launch_bounce_k<16, false>(a, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_bounce_stats(const TransferArgs& a, hipStream_t stream, unsigned long long* stats)
+{
+    if (a.count <= 0) return hipSuccess;
+    switch (a.K) {
+        case 1: return launch_bounce_k<1, false>(a, stream, stats);
+        case 4: return launch_bounce_k<4, false>(a, stream, stats);
+        case 9: return launch_bounce_k<9, false>(a, stream, stats);
+        case 16: return launch_bounce_k<16, false>(a, stream, stats);
         default: return hipErrorInvalidValue;
     }
 }

@@ -37,7 +37,7 @@ def test_binding_covers_the_header():
 
 
 def test_abi_version(lib):
-    assert lib.prtgs_abi_version() == 3
+    assert lib.prtgs_abi_version() == 4
 
 
 def test_size_queries(lib):
@@ -63,6 +63,10 @@ def test_size_queries(lib):
     ((64, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99, 2, 1.0), 1),     # unknown bounce mode
     ((64, 3, 0, 9, 3.0, 0.0, 1e-4, 0.0, 0.99, 1, 1.0), 1),     # more than 8 index bounces
     ((64, 3, 0, 2, 3.0, 0.0, 1e-4, 0.0, 0.99, 1, 0.0), 1),     # t_same = 0
+    ((64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0, 3, 0), 1),   # 3 sources per wave
+    ((64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0, 128, 0), 1), # 128 sources per wave
+    ((64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0, 16, 65), 1), # 65 direction parts
+    ((64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0, 16, -1), 1), # negative direction parts
 ])
 def test_transfer_validation(lib, desc, status):
     from paper_2408_03538_amd import _lib

@@ -170,17 +170,16 @@ def test_transfer_surface_sampled(prt, oracle_mod):
 
 
 @pytest.mark.parametrize("group", ["1", "4"])
-def test_transfer_source_ranges(prt, monkeypatch, group):
+def test_transfer_source_ranges(prt, group):
     """Chunked runs over leaf ranges reproduce the single run bit for bit
     under one work split (the fan kernel, 4 sources per wave; chunks of 700
     keep the groups of 4 aligned).  Across splits only the order of each ray's
     1 - alpha products differs: test_transfer_work_splits."""
     import torch
-    monkeypatch.setenv("PRTGS_GROUP", group)
     scene = as_f32(scenegen.random_cloud(3000, 12))
     sc = prt.Scene.from_arrays(scene)
     bvh = prt.build_bvh(sc)
-    params = prt.TransferParams(num_dirs=64, sh_bands=3)
+    params = prt.TransferParams(num_dirs=64, sh_bands=3, sources_per_wave=int(group))
     full = prt.precompute_transfer(sc, bvh, params)
     part = torch.zeros_like(full)
     for first in range(0, 3000, 700):
@@ -188,23 +187,21 @@ def test_transfer_source_ranges(prt, monkeypatch, group):
     assert torch.equal(full, part)
 
 
-def test_transfer_work_splits(prt, oracle_mod, monkeypatch):
+def test_transfer_work_splits(prt, oracle_mod):
     """Every work split (the fan kernel, 2 to 64 sources per wave) gives the
     same transfer up to the order in which a ray multiplies its hits' 1 - alpha
     (the packets differ, so their visit orders do): the SH projection is one
-    FP64 sum per source in direction order whatever the split.  A ray whose
+    compensated sum per source in direction order whatever the split.  A ray whose
     transmittance ends within rounding of T_eps may be cut off in one order
     and not in another, moving one term by at most 4 pi / S T_eps |Y|."""
     scene = as_f32(scenegen.surface_scene(4000, 21))
     sc = prt.Scene.from_arrays(scene)
     bvh = prt.build_bvh(sc)
     S, bands = 128, 4
-    params = prt.TransferParams(num_dirs=S, sh_bands=bands)
     outs = {}
     for g in (1, 2, 8, 16, 64):
-        monkeypatch.setenv("PRTGS_GROUP", str(g))
+        params = prt.TransferParams(num_dirs=S, sh_bands=bands, sources_per_wave=g)
         outs[g] = prt.precompute_transfer(sc, bvh, params, check=True).cpu().numpy().astype(np.float64)
-    monkeypatch.delenv("PRTGS_GROUP")
     ref = outs[8]
     for g, t in outs.items():
         d = np.abs(t - ref)
