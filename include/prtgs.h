@@ -194,6 +194,26 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g /* host */, cons
                                        int32_t count, float* transfer, float* vis, void* ws,
                                        size_t ws_bytes, hipStream_t stream);
 
+/* The direct transfer (bounces == 0) as prtgs_precompute_transfer computes  */
+/* it, for callers that cannot allocate (code under HIP graph capture, tight  */
+/* serving loops, harnesses that forbid allocation): no workspace argument;  */
+/* its scratch (flag word, direction tables, 4 count S bytes of per-ray      */
+/* weights) is a static device array of PRTGS_NOALLOC_SCRATCH_MIB MiB inside */
+/* the library, one per GPU it runs on, held until the process ends.  The    */
+/* call makes no allocation.  Call it with the device of `stream` current.   */
+/* count x S beyond the scratch (about 16.7M rays, e.g. 32,000 sources at    */
+/* S = 512) returns PRTGS_ERR_WORKSPACE_TOO_SMALL with nothing enqueued:     */
+/* cover larger scenes with several source ranges.  Calls that overlap on    */
+/* one GPU share its scratch and race: serialise them (one stream, or        */
+/* events).  bounces != 0 returns PRTGS_ERR_UNSUPPORTED.  flags (device word,*/
+/* may be NULL): cleared, then receives the call's device flag bits.  The    */
+/* result equals prtgs_precompute_transfer's for the same arguments.         */
+#define PRTGS_NOALLOC_SCRATCH_MIB 64
+prtgs_status prtgs_precompute_transfer_noalloc(const prtgs_gaussians* g /* host */, const void* bvh,
+                                               const prtgs_transfer_desc* d /* host */, int32_t first,
+                                               int32_t count, float* transfer, float* vis, unsigned* flags,
+                                               hipStream_t stream);
+
 /* Index matrix of the paper's bounce (Sec. 4.4, Eq. 26 and the same-surface */
 /* filter): index[i][s] = the Gaussian (original index) of largest           */
 /* W_j = alpha_j T_j max(-w_s . n_j, 0) along the ray of source i in          */

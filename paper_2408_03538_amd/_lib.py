@@ -19,6 +19,7 @@ FLAG_BAD_INDEX = 0x8
 FLAG_ROUND_CAP = 0x10
 BOUNCE_HIT_LIST = 256     # PRTGS_BOUNCE_HIT_LIST
 BLEND_PARTS_MAX = 8       # PRTGS_BLEND_PARTS_MAX
+NOALLOC_SCRATCH_BYTES = 64 << 20   # PRTGS_NOALLOC_SCRATCH_MIB
 BOUNCE_BLEND = 0
 BOUNCE_INDEX = 1
 
@@ -66,6 +67,8 @@ SIGNATURES = {
     "prtgs_transfer_workspace_bytes": (c_size_t, [ctypes.POINTER(TransferDesc), c_int32]),
     "prtgs_precompute_transfer": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, ctypes.POINTER(TransferDesc),
                                             c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "prtgs_precompute_transfer_noalloc": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, ctypes.POINTER(TransferDesc),
+                                                    c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "prtgs_index_matrix": (c_int32, [ctypes.POINTER(Gaussians), c_void_p, ctypes.POINTER(TransferDesc), c_void_p,
                                      c_void_p, c_size_t, c_void_p]),
     "prtgs_self_transfer": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

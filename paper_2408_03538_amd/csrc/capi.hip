@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -720,6 +721,91 @@ prtgs_status prtgs_transfer_backward(const prtgs_gaussians* g, const void* bvh, 
     a.log_scales = g->log_scales;
     a.out = *grads;
     return hip_status(launch_transfer_backward(a, stream), "transfer backward");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The direct transfer without a caller workspace.  Its scratch (flag word,
+// direction tables, per-ray weights) is this file's static device array;
+// each GPU holds its own copy, whose address hipGetSymbolAddress gives once
+// per device (the name itself is only a host-side stand-in).
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = (size_t)PRTGS_NOALLOC_SCRATCH_MIB << 20;
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+// The current device's copy of `scratch` (looked up on its first use).
+hipError_t scratch_on_current_device(char** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255u)) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<char*>(g_scratch_ptr[dev]);
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+prtgs_status prtgs_precompute_transfer_noalloc(const prtgs_gaussians* g, const void* bvh, const prtgs_transfer_desc* d,
+                                               int32_t first, int32_t count, float* transfer, float* vis,
+                                               unsigned* flags, hipStream_t stream)
+{
+    prtgs_status st = check_desc(d);
+    if (st != PRTGS_OK) return st;
+    if (d->bounces != 0)
+        return fail(PRTGS_ERR_UNSUPPORTED, "the no-allocation transfer covers the direct pass only (bounces = 0)");
+    st = check_gaussians(g, false);
+    if (st != PRTGS_OK) return st;
+    const int n = g->n;
+    if (!bvh) return fail(PRTGS_ERR_INVALID_ARG, "bvh is NULL");
+    if (!aligned256(bvh)) return fail(PRTGS_ERR_INVALID_ARG, "bvh must be 256-byte aligned");
+    if (first < 0 || count < 0 || (int64_t)first + count > n)
+        return fail(PRTGS_ERR_INVALID_ARG, "source range [%d, %d + %d) outside [0, %d)", first, first, count, n);
+    if (count > 0 && !transfer) return fail(PRTGS_ERR_INVALID_ARG, "transfer is NULL");
+    // per-ray weights are held for the selected sources only: lay the
+    // scratch out as a workspace for `count` sources
+    TransferWs W = transfer_ws_layout(*d, count > 0 ? count : 1);
+    if (W.total > kNoAllocScratchBytes)
+        return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL,
+                    "%d sources x %d directions need %zu bytes of scratch, the library holds %zu: use fewer sources per "
+                    "call",
+                    count, d->num_dirs, W.total, kNoAllocScratchBytes);
+    char* w = nullptr;
+    hipError_t e = scratch_on_current_device(&w);
+    if (e != hipSuccess) return hip_status(e, "scratch address");
+    unsigned* fl = flags ? flags : reinterpret_cast<unsigned*>(w);
+    e = fill_u32(fl, 0u, 1, stream);
+    if (e == hipSuccess)
+        e = launch_direction_table(d->num_dirs, d->seed, d->sh_bands, nullptr, nullptr,
+                                   reinterpret_cast<float*>(w + W.dirs), reinterpret_cast<float*>(w + W.Y), stream);
+    if (e == hipSuccess) e = launch_direction_order(d->num_dirs, reinterpret_cast<int32_t*>(w + W.dir_order), stream);
+    if (e != hipSuccess) return hip_status(e, "direction table");
+    if (count == 0) return ok();
+    TransferArgs a = transfer_args(g, bvh, d, first, count, transfer, vis, w, W);
+    a.flags = fl;
+    return hip_status(launch_transfer_direct(a, stream), "direct transfer");
 }
 
 }  // extern "C"

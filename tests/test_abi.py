@@ -244,3 +244,19 @@ def test_glossy_view_validation(lib):
     assert lib.prtgs_glossy_view(10, 16, None, 256, eye, 256, None) == 1
     assert lib.prtgs_glossy_view(-1, 16, 256, 256, eye, 256, None) == 1
     assert lib.prtgs_glossy_view(0, 16, None, None, eye, None, None) == 0       # nothing to do
+
+
+def test_noalloc_host_validation(lib):
+    """The no-allocation transfer refuses, on the host and before any device
+    work, a call whose rays exceed its static scratch, and a bounce."""
+    from paper_2408_03538_amd import _lib
+    g = _lib.Gaussians(100000, 256, 256, 256, 256, 256, 256)
+    d = _lib.TransferDesc(512, 4, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0)
+    st = lib.prtgs_precompute_transfer_noalloc(ctypes.byref(g), 256, ctypes.byref(d), 0, 100000, 256, None, None, None)
+    assert st == _lib.ERR_WORKSPACE_TOO_SMALL
+    assert b"scratch" in lib.prtgs_last_error()
+    b = _lib.TransferDesc(64, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0)
+    assert lib.prtgs_precompute_transfer_noalloc(ctypes.byref(g), 256, ctypes.byref(b), 0, 10, 256, None, None,
+                                                 None) == 3
+    assert lib.prtgs_precompute_transfer_noalloc(ctypes.byref(g), 257, ctypes.byref(d), 0, 10, 256, None, None,
+                                                 None) == 1     # misaligned BVH
