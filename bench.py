@@ -95,6 +95,8 @@ def parse():
                     help="only time the 3M x 64 relight in FP32, BF16 and F16 storage")
     ap.add_argument("--surface-only", action="store_true",
                     help="only the 100k surface workload (direct transfer; profiling runs)")
+    ap.add_argument("--index-only", action="store_true",
+                    help="only the million-splat index matrix (the paper's bounce; profiling runs)")
     return ap.parse_args()
 
 
@@ -177,6 +179,19 @@ def main():
     log("generating the million-splat workload")
     arr, sc, params, light = workload_setup(prt, torch, scenegen, "million")
     n, S = sc.n, params.num_dirs
+    if args.index_only:
+        bvh = prt.build_bvh(sc)
+        p_idx = prt.TransferParams(num_dirs=S, sh_bands=params.sh_bands, bounce_mode="index", bounces=1)
+        ws = prt.Workspace()
+        for _ in range(max(1, args.steps)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            idx = prt.index_matrix(sc, bvh, p_idx, workspace=ws)
+            b.record()
+            torch.cuda.synchronize()
+            log(f"index matrix (direct pass + index walk): {a.elapsed_time(b):.1f} ms")
+            del idx
+        return
     res = time_steps(prt, torch, np, sc, params, light, args.steps, args.warmup)
     ms_step = res["ms_step"]
     log(f"step {ms_step:.1f} ms: build {res['build']:.2f} ms, transfer {res['transfer']:.1f} ms, "

@@ -25,9 +25,17 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 # Default cutoffs: 3-sigma hit extent, peaks behind the origin ignored,
 # transmittance below 1e-4 is opaque, no alpha floor, alpha clamped at 0.99.
-DEFAULT_CUT = dict(sigma_cut=3.0, t_min=0.0, T_eps=1e-4, alpha_min=0.0, alpha_max=0.99)
-# Margins inside which an FP32 evaluation may resolve a predicate either way.
-DEFAULT_MARGINS = (1e-6, 3e-5, 3e-6, 1e-3, 1e-5)
+# c_min: a ray is traced iff n . w > c_min; 0 as on the GPU path (other values
+# only move the hemisphere threshold, to pin the deviation bound).
+DEFAULT_CUT = dict(sigma_cut=3.0, t_min=0.0, T_eps=1e-4, alpha_min=0.0, alpha_max=0.99, c_min=0.0)
+# Margins inside which an FP32 evaluation may resolve a predicate either way
+# (the forms are in prtgs_oracle.c): |c| <= 1e-6; |d^2 - sigma_cut^2| <=
+# 5e-5 (1 + kappa); |t* - t_min| <= 8e-5 (1 + d) / |W w| + 1e-5 |t*|;
+# |T / T_eps - 1| <= 1e-4; two peak depths tied within the sum of their t*
+# margins.  Each is at least 10x the largest error of a float32 model of the
+# GPU's evaluation on the surface and million-splat workloads
+# (tests/test_oracle_margins.py).
+DEFAULT_MARGINS = (1e-6, 5e-5, 8e-5, 1e-4, 1e-5)
 
 
 def build(force: bool = False) -> str:
@@ -65,7 +73,8 @@ def _cut_array(cut):
     c = dict(DEFAULT_CUT)
     if cut:
         c.update(cut)
-    return np.array([c["sigma_cut"], c["t_min"], c["T_eps"], c["alpha_min"], c["alpha_max"]], dtype=np.float64)
+    return np.array([c["sigma_cut"], c["t_min"], c["T_eps"], c["alpha_min"], c["alpha_max"], c["c_min"]],
+                    dtype=np.float64)
 
 
 def default_threads() -> int:
@@ -123,11 +132,15 @@ def _scene_arrays(scene):
 
 
 def direct_transfer(scene, num_dirs, bands, seed=0, cut=None, sources=None, want_vis=False,
-                    want_allow=False, margins=DEFAULT_MARGINS, threads=None, dirs=None, Y=None):
+                    want_allow=False, margins=DEFAULT_MARGINS, threads=None, dirs=None, Y=None,
+                    want_vis_bounds=False):
     """Direct (visibility) transfer t[count, K] of the listed sources.
 
     Returns dict(t=..., vis=[count,S] or None (-1 marks untraced rays),
-    allow=[count,K] or None).
+    allow=[count,K] or None, vis_lo / vis_hi=[count,S] or None: the range
+    of each ray's V over the other resolutions of its near-threshold
+    predicates, -1 where the ray is not traced and its hemisphere test is
+    not ambiguous).
     """
     means, quats, log_scales, opacity, normals = _scene_arrays(scene)
     n = means.shape[0]
@@ -139,12 +152,14 @@ def direct_transfer(scene, num_dirs, bands, seed=0, cut=None, sources=None, want
     t = np.empty((count, K))
     vis = np.empty((count, num_dirs)) if want_vis else None
     allow = np.empty((count, K)) if want_allow else None
+    vlo = np.empty((count, num_dirs)) if want_vis_bounds else None
+    vhi = np.empty((count, num_dirs)) if want_vis_bounds else None
     mar = np.array(margins, dtype=np.float64) if (want_allow or margins is not None) else None
     _lib().ora_direct(ctypes.c_int(n), _p(means), _p(quats), _p(log_scales), _p(opacity), _p(normals),
                       ctypes.c_int(num_dirs), _p(_f64(dirs)), ctypes.c_int(K), _p(_f64(Y)),
                       _p(_cut_array(cut)), _p(mar), _p(src), ctypes.c_int(count), _p(t), _p(vis),
-                      _p(allow), ctypes.c_int(threads or default_threads()))
-    return dict(t=t, vis=vis, allow=allow)
+                      _p(allow), _p(vlo), _p(vhi), ctypes.c_int(threads or default_threads()))
+    return dict(t=t, vis=vis, allow=allow, vis_lo=vlo, vis_hi=vhi)
 
 
 def hit_set(scene, num_dirs, seed=0, cut=None, sources=None, margins=DEFAULT_MARGINS, threads=None):

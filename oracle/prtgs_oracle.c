@@ -30,15 +30,28 @@
  *   cut[2] T_eps     : a transmittance below T_eps counts as 0 (opaque)
  *   cut[3] alpha_min : hits with alpha < alpha_min are ignored
  *   cut[4] alpha_max : alpha is clamped to alpha_max
+ *   cut[5] c_min     : a ray is traced iff c = n_i . w > c_min (0 on the GPU
+ *                      path; other values only move the hemisphere threshold
+ *                      to check the deviation bound of its near-threshold rays)
  *
  * Near-threshold margins (array `mar`), used only to bound how much a result
  * computed in another precision may legitimately differ (both resolutions of
  * a predicate that lies within rounding of its threshold are correct):
  *   mar[0] |c| below which the hemisphere test is ambiguous
- *   mar[1] margin of d^2 against sigma_cut^2, times (1 + |mu_i - mu_j| / s_min,j)
- *   mar[2] margin of t* against t_min, times (1 + |mu_i - mu_j|)
- *   mar[3] relative margin of the transmittance against T_eps
- *   mar[4] margin under which two peak distances t* count as tied
+ *   mar[1] margin of d^2 against sigma_cut^2, times (1 + kappa_j)
+ *   mar[2] margin of t* against t_min: mar[2] (1 + d) / |W w| + mar[4] |t*|
+ *   mar[3] relative margin of the transmittance against T_eps (and t_same)
+ *   mar[4] the relative part of the t* margin; two peak depths count as tied
+ *          when they differ by at most the sum of their t* margins
+ * with kappa_j = s_max,j / s_min,j the anisotropy of Gaussian j, d = sqrt(d^2)
+ * and |W w| = sqrt(w^T Sigma_j^-1 w).  These are the error scales of an FP32
+ * evaluation that forms p = W x from the exact offset x between the ray point
+ * and the centre (W = diag(1/s) R^T, Eq. 2) and refines t* by a Newton step:
+ * rounding W and W x moves the thin-axis component of p by a few eps times
+ * |x| / s_min, and |x| <= 3 s_max for a Gaussian the ray reaches, so d^2
+ * moves by O(eps kappa); the step leaves t* off by the error of p along W w
+ * over |W w|, O(eps (1 + d) / |W w|).  Neither depends on the distance to
+ * the ray origin.
  */
 #include <math.h>
 #include <stdint.h>
@@ -158,7 +171,8 @@ typedef struct {
     double mu[3];
     double sinv[9]; /* row-major Sigma^{-1} */
     double o;
-    double smin;    /* smallest scale, for the rounding margins only */
+    double smin;    /* smallest and largest scale, for the rounding margins only */
+    double smax;
 } OraGauss;
 
 static void ora_rotation(const double* q, double* R)
@@ -178,10 +192,12 @@ static OraGauss* ora_setup(int n, const double* means, const double* quats,
         double R[9], inv2[3];
         ora_rotation(quats + 4 * (size_t)j, R);
         g[j].smin = INFINITY;
+        g[j].smax = 0.0;
         for (int a = 0; a < 3; ++a) {
             double s = exp(log_scales[3 * (size_t)j + a]);
             inv2[a] = 1.0 / (s * s);
             if (s < g[j].smin) g[j].smin = s;
+            if (s > g[j].smax) g[j].smax = s;
         }
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) {
@@ -210,12 +226,19 @@ static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1]
 typedef struct {
     double t, alpha;
     double alpha_if_hit; /* alpha it has, or would have were it a hit */
+    double mt;           /* margin of t (0 without margins) */
     int j;
     int amb; /* the hit predicate is within its margin */
 } OraHit;
 
+/* The t* margin at peak depth t, d^2 and wSw = w^T Sigma^-1 w (mar[2] above). */
+static double ora_t_margin(const double* mar, double t, double d2, double wSw)
+{
+    return mar ? mar[2] * (1.0 + sqrt(fmax(d2, 0.0))) / sqrt(wSw) + mar[4] * fabs(t) : 0.0;
+}
+
 static int ora_test(const OraGauss* g, const double* org, const double* w, const double* cut,
-                    const double* mar, double* t_out, double* alpha_out, int* amb_out)
+                    const double* mar, double* t_out, double* alpha_out, int* amb_out, double* mt_out)
 {
     double rel[3] = {g->mu[0] - org[0], g->mu[1] - org[1], g->mu[2] - org[2]};
     double sw[3];
@@ -235,11 +258,9 @@ static int ora_test(const OraGauss* g, const double* org, const double* w, const
     }
     int amb = 0;
     if (mar) {
-        /* FP32 evaluation error of d^2 grows with the distance in units of the
-         * thinnest axis, that of t* with the distance itself */
-        double dist = sqrt(dot3(rel, rel));
-        double md2 = mar[1] * (1.0 + dist / g->smin);
-        double mt = mar[2] * (1.0 + dist);
+        /* FP32 evaluation error of d^2 and t* (see mar[] above) */
+        double md2 = mar[1] * (1.0 + g->smax / g->smin);
+        double mt = ora_t_margin(mar, t, d2, dot3(w, sw));
         if (fabs(d2 - cut2) <= md2 && t > cut[1] - mt) amb = 1;
         if (fabs(t - cut[1]) <= mt && d2 <= cut2 + md2) amb = 1;
         if (cut[3] > 0.0) {
@@ -250,6 +271,7 @@ static int ora_test(const OraGauss* g, const double* org, const double* w, const
     *t_out = t;
     *alpha_out = alpha;
     *amb_out = amb;
+    if (mt_out) *mt_out = ora_t_margin(mar, t, d2, dot3(w, sw));
     return hit;
 }
 
@@ -278,7 +300,7 @@ static double ora_ray_vis(const OraGauss* g, int n, int self, const double* w, c
         if (j == self) continue;
         double t, alpha;
         int amb;
-        int hit = ora_test(&g[j], org, w, cut, mar, &t, &alpha, &amb);
+        int hit = ora_test(&g[j], org, w, cut, mar, &t, &alpha, &amb, NULL);
         if (hit) v *= 1.0 - alpha;
         if (amb) {
             /* the other resolution: hit with the alpha it would have */
@@ -316,11 +338,15 @@ static int ora_threads(int requested)
 /* Direct transfer of the listed sources (Eq. 29 without the receiver's BRDF):
  *   t[i][k] = (4 pi / S) sum_s V_is max(0, n_i . w_s) Y_k(w_s).
  * vis[i][s] receives V for traced rays and -1 for rays with n_i . w_s <= 0.
- * allow[i][k] receives the legitimate-deviation bound of each coefficient. */
+ * allow[i][k] receives the legitimate-deviation bound of each coefficient.
+ * vlo/vhi[i][s] (may be NULL) receive the range of V over the other
+ * resolutions of the ray's near-threshold predicates (lo = hi = V without
+ * any), for rays that are traced or whose hemisphere test is ambiguous, and
+ * -1 for the rest. */
 int ora_direct(int n, const double* means, const double* quats, const double* log_scales,
                const double* opacity, const double* normals, int S, const double* dirs, int K,
                const double* Y, const double* cut, const double* mar, const int* sources, int count,
-               double* t_out, double* vis_out, double* allow_out, int threads)
+               double* t_out, double* vis_out, double* allow_out, double* vlo_out, double* vhi_out, int threads)
 {
     OraGauss* g = ora_setup(n, means, quats, log_scales, opacity);
     double wq = 4.0 * ORA_PI / (double)S;
@@ -338,22 +364,26 @@ int ora_direct(int n, const double* means, const double* quats, const double* lo
         for (int s = 0; s < S; ++s) {
             const double* w = dirs + 3 * (size_t)s;
             double c = dot3(nrm, w);
-            int amb_c = mar && fabs(c) <= mar[0];
-            double vis = -1.0;
-            if (c > 0.0 || amb_c) {
+            int amb_c = mar && fabs(c - cut[5]) <= mar[0];
+            double vis = -1.0, vlo = -1.0, vhi = -1.0;
+            if (c > cut[5] || amb_c) {
                 double lo, hi;
                 double v = ora_ray_vis(g, n, i, w, cut, mar, &lo, &hi);
-                if (c > 0.0) {
+                vlo = mar ? fmin(lo, v) : v;
+                vhi = mar ? fmax(hi, v) : v;
+                if (c > cut[5]) {
                     vis = v;
                     for (int k = 0; k < K; ++k) t[k] += wq * v * c * Y[(size_t)s * K + k];
                 }
                 if (al) {
-                    double dev = (c > 0.0 ? c : 0.0) * (hi - lo);
+                    double dev = (c > cut[5] ? c : 0.0) * (hi - lo);
                     if (amb_c) dev += fabs(c);
                     for (int k = 0; k < K; ++k) al[k] += wq * fabs(Y[(size_t)s * K + k]) * dev;
                 }
             }
             if (vis_out) vis_out[(size_t)q * S + s] = vis;
+            if (vlo_out) vlo_out[(size_t)q * S + s] = vlo;
+            if (vhi_out) vhi_out[(size_t)q * S + s] = vhi;
         }
     }
     free(g);
@@ -393,12 +423,12 @@ int ora_hit_set(int n, const double* means, const double* quats, const double* l
         for (int s = 0; s < S; ++s) {
             const double* w = dirs + 3 * (size_t)s;
             double c = dot3(nrm, w);
-            if (!(c > 0.0 || (mar && fabs(c) <= mar[0]))) continue;
+            if (!(c > cut[5] || (mar && fabs(c - cut[5]) <= mar[0]))) continue;
             for (int j = 0; j < n; ++j) {
                 if (j == i) continue;
                 double t, alpha;
                 int amb;
-                if (ora_test(&g[j], g[i].mu, w, cut, mar, &t, &alpha, &amb) || amb) mark[j] = 1;
+                if (ora_test(&g[j], g[i].mu, w, cut, mar, &t, &alpha, &amb, NULL) || amb) mark[j] = 1;
             }
         }
     }
@@ -451,14 +481,14 @@ int ora_bounce(int n, const double* means, const double* quats, const double* lo
             for (int s = 0; s < S; ++s) {
                 const double* w = dirs + 3 * (size_t)s;
                 double c = dot3(nrm, w);
-                int amb_c = mar && fabs(c) <= mar[0];
-                if (!(c > 0.0 || amb_c)) continue;
+                int amb_c = mar && fabs(c - cut[5]) <= mar[0];
+                if (!(c > cut[5] || amb_c)) continue;
                 int nh = 0, amb_ray = 0;
                 for (int j = 0; j < n; ++j) {
                     if (j == i) continue;
-                    double t, alpha;
+                    double t, alpha, mt;
                     int amb;
-                    int hit = ora_test(&g[j], g[i].mu, w, cut, mar, &t, &alpha, &amb);
+                    int hit = ora_test(&g[j], g[i].mu, w, cut, mar, &t, &alpha, &amb, &mt);
                     if (amb) amb_ray = 1;
                     if (amb && !hit) {
                         /* keep it in the list, marked, with the alpha it would
@@ -466,6 +496,7 @@ int ora_bounce(int n, const double* means, const double* quats, const double* lo
                         hits[nh].t = t;
                         hits[nh].alpha = -1.0;
                         hits[nh].alpha_if_hit = ora_alpha_if_hit(&g[j], g[i].mu, w, cut);
+                        hits[nh].mt = mt;
                         hits[nh].j = j;
                         hits[nh].amb = 1;
                         ++nh;
@@ -473,6 +504,7 @@ int ora_bounce(int n, const double* means, const double* quats, const double* lo
                         hits[nh].t = t;
                         hits[nh].alpha = alpha;
                         hits[nh].alpha_if_hit = alpha;
+                        hits[nh].mt = mt;
                         hits[nh].j = j;
                         hits[nh].amb = amb;
                         ++nh;
@@ -480,7 +512,7 @@ int ora_bounce(int n, const double* means, const double* quats, const double* lo
                 }
                 qsort(hits, (size_t)nh, sizeof(OraHit), ora_hit_cmp);
                 double T = 1.0;
-                double cpos = c > 0.0 ? c : 0.0;
+                double cpos = c > cut[5] ? c : 0.0;
                 double bound[3 * 64];
                 int K3 = 3 * K;
                 for (int k = 0; k < K3 && k < 3 * 64; ++k) bound[k] = 0.0;
@@ -513,7 +545,7 @@ int ora_bounce(int n, const double* means, const double* quats, const double* lo
                             }
                         if (!ended) {
                             double aa = hits[h].alpha_if_hit;
-                            int tied = h > 0 && fabs(hits[h].t - hits[h - 1].t) <= mar[4] * (1.0 + fabs(hits[h].t));
+                            int tied = h > 0 && fabs(hits[h].t - hits[h - 1].t) <= hits[h].mt + hits[h - 1].mt;
                             if (tied) {
                                 amb_ray = 1;
                                 units += 2.0 * aa * run_alpha * T_run;
@@ -531,7 +563,7 @@ int ora_bounce(int n, const double* means, const double* quats, const double* lo
                     if (ended || hits[h].alpha < 0.0) continue;
                     double a = hits[h].alpha;
                     double wgt = a * T;
-                    if (c > 0.0)
+                    if (c > cut[5])
                         for (int ch = 0; ch < 3; ++ch)
                             for (int k = 0; k < K; ++k)
                                 out[ch * K + k] += wq * cpos * wgt * rho[ch] / ORA_PI * td[k];
@@ -545,7 +577,7 @@ int ora_bounce(int n, const double* means, const double* quats, const double* lo
                     if (T < cut[2]) ended = 1;
                 }
                 if (al && (amb_ray || amb_c)) {
-                    double cc = amb_c ? fmax(cpos, mar[0]) : cpos;
+                    double cc = amb_c ? fmax(cpos, fabs(c) + mar[0]) : cpos;
                     units += 2.0 * (1.0 + mar[3]) * cut[2] * exp(fmin(A, 700.0));
                     if (amb_c) units += 1.0;   /* the ray may not be traced at all */
                     if (units > 2.0) units = 2.0;
@@ -597,19 +629,20 @@ int ora_index(int n, const double* means, const double* quats, const double* log
             for (int s = 0; s < S; ++s) {
                 const double* w = dirs + 3 * (size_t)s;
                 double c = dot3(nrm, w);
-                int amb = mar && fabs(c) <= mar[0];
+                int amb = mar && fabs(c - cut[5]) <= mar[0];
                 int best = -1;
-                if (c > 0.0 || amb) {
+                if (c > cut[5] || amb) {
                     int nh = 0;
                     for (int j = 0; j < n; ++j) {
                         if (j == i) continue;
-                        double t, alpha;
+                        double t, alpha, mt;
                         int a_j;
-                        int hit = ora_test(&g[j], g[i].mu, w, cut, mar, &t, &alpha, &a_j);
+                        int hit = ora_test(&g[j], g[i].mu, w, cut, mar, &t, &alpha, &a_j, &mt);
                         if (hit || a_j) {
                             hits[nh].t = t;
                             hits[nh].alpha = hit ? alpha : -1.0;
                             hits[nh].alpha_if_hit = hit ? alpha : ora_alpha_if_hit(&g[j], g[i].mu, w, cut);
+                            hits[nh].mt = mt;
                             hits[nh].j = j;
                             hits[nh].amb = a_j;
                             ++nh;
@@ -623,7 +656,7 @@ int ora_index(int n, const double* means, const double* quats, const double* log
                         walked = h + 1;
                         double da = 0.0;
                         if (mar && hits[h].amb) da += hits[h].alpha_if_hit;
-                        if (mar && h > 0 && fabs(hits[h].t - hits[h - 1].t) <= mar[4] * (1.0 + fabs(hits[h].t)))
+                        if (mar && h > 0 && fabs(hits[h].t - hits[h - 1].t) <= hits[h].mt + hits[h - 1].mt)
                             da += fmax(hits[h].alpha_if_hit, hits[h - 1].alpha_if_hit);
                         pa[h + 1] = pa[h] + da;
                         const double* nj = normals + 3 * (size_t)hits[h].j;
@@ -664,7 +697,7 @@ int ora_index(int n, const double* means, const double* quats, const double* log
                         }
                         if (eps_amb && bestW < 2.0 * cut[2]) amb = 1;
                     }
-                    if (!(c > 0.0)) best = -1;
+                    if (!(c > cut[5])) best = -1;
                 }
                 idx_out[(size_t)q * S + s] = best;
                 if (amb_out) amb_out[(size_t)q * S + s] = (unsigned char)(amb != 0);

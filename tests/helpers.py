@@ -22,3 +22,37 @@ def assert_transfer_parity(gpu, ref, allow, tol=1e-4, what="transfer"):
                              f"{(err - bound).max():.3e}; first {idx.tolist()}; "
                              f"gpu {gpu[tuple(idx[0])]:.7f} ref {ref[tuple(idx[0])]:.7f} allow {allow[tuple(idx[0])]:.3e}")
     return float(err.max())
+
+
+# Relative FP32 error allowed on a ray's transmittance: 10x the largest error
+# of the float32 model of the GPU's product of (1 - alpha) over its hits
+# (tests/test_oracle_margins.py measured 3.6e-6).
+VIS_REL_TOL = 4e-5
+
+
+def assert_ray_vis(gpu, ref, cos, mar_c, what="visibility"):
+    """Per-ray parity of the visibility.  gpu: [count, S] V from the GPU (-1 =
+    not traced); ref: the oracle's direct_transfer with want_vis and
+    want_vis_bounds; cos: [count, S] n . w in FP64; mar_c: the hemisphere
+    margin.  A ray whose hemisphere test is unambiguous is traced by both or
+    by neither; one within the margin may go either way.  Every ray the GPU
+    traces has V within [vis_lo, vis_hi] (the range over the other
+    resolutions of its near-threshold predicates; one value for most rays) up
+    to FP32 rounding of the product.  Returns (rays traced by the GPU, rays
+    with a range wider than the rounding tolerance)."""
+    gpu = np.asarray(gpu, dtype=np.float64)
+    lo, hi, vis = ref["vis_lo"], ref["vis_hi"], ref["vis"]
+    amb_c = np.abs(cos) <= mar_c
+    traced = gpu != -1.0
+    assert not (traced & (vis == -1.0) & ~amb_c).any(), f"{what}: the GPU traced a ray below the horizon"
+    assert not (~traced & (vis != -1.0) & ~amb_c).any(), f"{what}: the GPU skipped a ray above the horizon"
+    assert (lo[traced] >= 0.0).all()
+    tol = VIS_REL_TOL * hi + 1e-9
+    out = traced & ~((gpu >= lo - tol) & (gpu <= hi + tol))
+    if out.any():
+        idx = np.argwhere(out)[:5]
+        r, c = idx[0]
+        raise AssertionError(f"{what}: {out.sum()} rays outside their range; first {idx.tolist()}: gpu {gpu[r, c]:.7f} "
+                             f"range [{lo[r, c]:.7f}, {hi[r, c]:.7f}] oracle {vis[r, c]:.7f}")
+    wide = traced & (hi - lo > tol)
+    return int(traced.sum()), int(wide.sum())

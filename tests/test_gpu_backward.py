@@ -33,11 +33,14 @@ def _gpu_grads(prt, scene, S, bands, light, target):
     loss.backward()
     out = {k: ten[k].grad.cpu().numpy().astype(np.float64) for k in KEYS}
     out["light"] = L.grad.cpu().numpy().astype(np.float64)
-    return out, float(loss)
+    return out, float(loss.detach())
 
 
-def _compare(g, ref, rel=1e-3, what=""):
-    """Per component |g - r| <= rel max(|r|, 1e-2 |r|_inf), and normwise."""
+def _compare(g, ref, allow, rel=1e-3, what=""):
+    """Per component |g - r| <= rel max(|r|, 1e-2 |r|_inf) + allow (the
+    oracle's bound for decisions within FP32 rounding of a threshold), and
+    the normwise relative error <= rel.  Returns the share of components that
+    needed their allowance."""
     g = np.asarray(g, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     inf = np.abs(ref).max()
@@ -45,16 +48,25 @@ def _compare(g, ref, rel=1e-3, what=""):
         assert np.abs(g).max() < 1e-6, what
         return 0.0
     tol = rel * np.maximum(np.abs(ref), 1e-2 * inf)
-    bad = np.abs(g - ref) > tol
-    frac = bad.mean()
+    err = np.abs(g - ref)
+    bad = err > tol + allow
+    if bad.any():
+        i = tuple(np.argwhere(bad)[0])
+        raise AssertionError(f"{what}: {bad.sum()} of {bad.size} components off; first {i}: gpu {g[i]:.6e} "
+                             f"ref {ref[i]:.6e} tol {tol[i]:.2e} allow {allow[i]:.2e}")
     normwise = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     assert normwise <= rel, f"{what}: normwise relative error {normwise:.2e}"
-    return frac
+    return float((err > tol).mean())
 
 
 @pytest.mark.parametrize("name", ["dense", "subset500"])
 def test_adjoint_matches_oracle_gradient(prt, oracle_mod, name):
-    from oracle.grad import loss_and_grads
+    """The adjoint of transfer + relight under an L2 loss against the FP64
+    autograd gradient of the oracle's forward, component by component within
+    1e-3 relative (floor 1e-2 of the tensor's largest); a component may
+    exceed that only by the oracle's bound for decisions within FP32 rounding
+    of their thresholds (each reversed alone, its change summed)."""
+    from oracle.grad import gradient_allowance, loss_and_grads
     if name == "dense":
         scene = scenegen.random_cloud(300, 91)
         scene["means"] *= 0.25                   # crowded: many hits per ray
@@ -68,19 +80,22 @@ def test_adjoint_matches_oracle_gradient(prt, oracle_mod, name):
     target = as_f32({"t": scenegen.colour_targets(n, 1, scenegen.SEED_TARGET + 4)})["t"]
     g, loss = _gpu_grads(prt, scene, S, bands, light, target)
     ref = loss_and_grads(scene, S, bands, light, target, chunk=8)
+    allow = gradient_allowance(scene, S, bands, light, target)
     assert abs(loss - ref["loss"]) <= 1e-4 * abs(ref["loss"])
-    fracs = {}
+    used = {}
     for k in KEYS + ("light",):
-        fracs[k] = _compare(g[k], ref["grads"][k], what=k)
-    # components off by more than 1e-3 relative: only those touched by rays
-    # whose cut-off decisions lie within FP32 rounding of a threshold
-    assert max(fracs.values()) < 0.01, fracs
-    print(name, {k: f"{v:.4f}" for k, v in fracs.items()})
+        used[k] = _compare(g[k], ref["grads"][k], allow["grads"][k], what=k)
+    print(name, f"{allow['items']} near-threshold decisions; share of components within their allowance only:",
+          {k: f"{v:.4f}" for k, v in used.items()})
 
 
 def test_adjoint_central_differences(prt, oracle_mod):
-    """64 random parameters: GPU adjoint against central differences
-    (h = 1e-3, and h / 4 to detect cut-off crossings) of the FP64 oracle."""
+    """64 random parameters: GPU adjoint against central differences of the
+    FP64 oracle forward, steps h = 1e-3 and h / 4 (means: in units of the
+    Gaussian's smallest scale, the length its alpha varies over), combined by
+    Richardson extrapolation; a parameter whose two estimates disagree has a
+    cut-off decision inside the step and is skipped.  Within 1e-3 of
+    max(|estimate|, 1e-2 of the largest adjoint component of that input)."""
     scene = as_f32(scenegen.surface_scene(400, 92))
     n = scene["means"].shape[0]
     S, bands = 64, 4
@@ -93,25 +108,27 @@ def test_adjoint_central_differences(prt, oracle_mod):
         return 0.5 * ((oracle_mod.relight(t[:, None, :], light) - target) ** 2).sum()
 
     rng = np.random.default_rng(scenegen.SEED_FD_PICK)
-    picks = [(KEYS[rng.integers(5)], None) for _ in range(64)]
     checked = 0
-    for key, _ in picks:
+    for _ in range(64):
+        key = KEYS[rng.integers(5)]
         arr = scene[key]
         idx = tuple(int(rng.integers(d)) for d in arr.shape)
+        h0 = 1e-3 * (np.exp(scene["log_scales"][idx[0]]).min() if key == "means" else 1.0)
         est = []
-        for h in (1e-3, 2.5e-4):
+        for h in (h0, h0 / 4):
             vals = []
             for sgn in (1, -1):
                 pert = {k: v.copy() for k, v in scene.items()}
                 pert[key][idx] += sgn * h
                 vals.append(loss(pert))
             est.append((vals[0] - vals[1]) / (2 * h))
-        scale = max(abs(est[1]), 1e-2 * np.abs(g[key]).max(), 1e-6)
+        scale = max(abs(est[1]), 1e-2 * np.abs(g[key]).max(), 1e-9)
         if abs(est[0] - est[1]) > 2e-3 * scale:
             continue                               # a cut-off crossed inside the step
         checked += 1
-        assert abs(g[key][idx] - est[1]) <= 5e-3 * scale, (key, idx, g[key][idx], est)
-    assert checked >= 32
+        rich = (16.0 * est[1] - est[0]) / 15.0
+        assert abs(g[key][idx] - rich) <= 1e-3 * scale, (key, idx, g[key][idx], est)
+    assert checked >= 40
 
 
 def test_backward_accumulates(prt):

@@ -64,34 +64,112 @@ def test_bounce_source_count_not_whole_blocks(prt, oracle_mod, n_surface):
 
 def test_bounce_many_faint_hits(prt, oracle_mod):
     """A crowded, faint cloud: rays meet hundreds of Gaussians before the
-    transmittance falls below T_eps (or never do), so each ray needs several
-    rounds of the 64-entry hit list."""
+    transmittance falls below T_eps (or never do), so a ray can list more hits
+    than its hit list holds in one round (PRTGS_BOUNCE_HIT_LIST) and needs
+    further rounds."""
+    from paper_2408_03538_amd import _lib
     scene = scenegen.random_cloud(1500, 23)
     scene["means"] *= 0.3
     scene["opacity"] *= 0.04
     scene = as_f32(scene)
     n = scene["means"].shape[0]
     S, bands = 32, 3
-    # hits along one ray (3-sigma ellipsoids crossed ahead of the origin)
-    o, w = scene["means"][0].astype(np.float64), np.array([0.6, 0.0, 0.8])
+    src = np.random.default_rng(4).choice(n, 60, replace=False)
+    # hits along the sampled sources' rays (3-sigma ellipsoids crossed ahead of
+    # the origin): some ray has more than a list holds
     R = np.stack([_rot(q) for q in scene["quats"].astype(np.float64)])
     inv_s2 = np.exp(-2.0 * scene["log_scales"].astype(np.float64))
     Ainv = np.einsum("nij,nj,nkj->nik", R, inv_s2, R)
-    dx = scene["means"] - o
-    a = np.einsum("i,nij,j->n", w, Ainv, w)
-    b = np.einsum("i,nij,nj->n", w, Ainv, dx)
-    c = np.einsum("ni,nij,nj->n", dx, Ainv, dx)
-    d2 = c - b * b / a
-    assert ((d2 < 9.0) & (b / a > 0)).sum() > 64
+    dirs = oracle_mod.directions(S)
+    most = 0
+    for i in src:
+        o = scene["means"][i].astype(np.float64)
+        dx = scene["means"] - o
+        for w in dirs[scene["normals"][i] @ dirs.T > 0]:
+            a = np.einsum("i,nij,j->n", w, Ainv, w)
+            b = np.einsum("i,nij,nj->n", w, Ainv, dx)
+            c = np.einsum("ni,nij,nj->n", dx, Ainv, dx)
+            most = max(most, int(((c - b * b / a < 9.0) & (b / a > 0)).sum()))
+    assert most > _lib.BOUNCE_HIT_LIST, most
     params = prt.TransferParams(num_dirs=S, sh_bands=bands, bounces=1)
     sc = prt.Scene.from_arrays(scene)
     bvh = prt.build_bvh(sc, check=True)
     t = prt.precompute_transfer(sc, bvh, params, check=True).cpu().numpy()
-    src = np.random.default_rng(4).choice(n, 60, replace=False)
+    st = prt.traversal_stats(sc, bvh, params)
+    assert st["rounds"] > st["traced_rays"]          # some rays overflowed their list
     ref = oracle_mod.full_transfer(scene, S, bands, 1, sources=src, want_allow=True)
     err = assert_transfer_parity(t[src], ref["t"], ref["allow"], what="bounce transfer")
     assert np.abs(ref["t_ind"]).max() > 1e-2
     print(f"faint cloud: bounce max |dt| = {err:.2e}, max |t_ind| = {np.abs(ref['t_ind']).max():.3f}")
+
+
+def _million_recipe(n_surface, per_shell, seed):
+    """The million-splat recipe (surface scene + 20 ellipsoid shells) at a
+    size the brute-force oracle finishes."""
+    return scenegen._concat([scenegen.surface_scene(n_surface, seed), scenegen.shells(20, per_shell, seed + 1)])
+
+
+@pytest.mark.parametrize("S", [512, 256])
+def test_bounce_parity_million_launch_shape(prt, oracle_mod, S):
+    """The launch shape of the million-splat workload: 16 sources per wave
+    and 64 direction parts, of which the blend keeps 8 with sums of their own
+    (each holding 16 direction batches at S = 512), on an 8,000-splat scene of
+    the same recipe.  24 sampled sources against the oracle's full transfer
+    (direct + bounce); the index matrix of the paper's bounce in the same
+    launch shape against the oracle's.  A part dropped or added twice moves
+    the bounce term by an eighth of its size, far beyond the allowance."""
+    scene = as_f32(_million_recipe(1600, 320, 41))
+    n = scene["means"].shape[0]
+    sc = prt.Scene.from_arrays(scene)
+    bvh = prt.build_bvh(sc, check=True)
+    params = prt.TransferParams(num_dirs=S, sh_bands=4, bounces=1, sources_per_wave=16, direction_parts=64)
+    t = prt.precompute_transfer(sc, bvh, params, check=True).cpu().numpy()
+    src = np.random.default_rng(43).choice(n, 24, replace=False)
+    print(f"million-shape bounce S = {S}: oracle on 24 sources", flush=True)
+    ref = oracle_mod.full_transfer(scene, S, 4, 1, sources=src, want_allow=True)
+    err = assert_transfer_parity(t[src], ref["t"], ref["allow"], what="bounce transfer")
+    ind = np.abs(ref["t_ind"][:, :, 0])
+    assert np.median(ind / (1e-4 + ref["allow"][:, :, 0])) > 8.0    # an eighth of the term is visible
+    # the same sums in one part: the regrouping moves only the last bits
+    one = prt.precompute_transfer(sc, bvh, prt.TransferParams(num_dirs=S, sh_bands=4, bounces=1, sources_per_wave=16,
+                                                              direction_parts=1), check=True).cpu().numpy()
+    assert np.abs(one - t).max() <= 1e-5 * (1.0 + np.abs(t).max())
+    pidx = prt.TransferParams(num_dirs=S, sh_bands=4, bounce_mode="index", bounces=1, sources_per_wave=16,
+                              direction_parts=64)
+    idx = prt.index_matrix(sc, bvh, pidx, check=True).cpu().numpy()
+    ref_idx, amb = oracle_mod.index_matrix(scene, S, sources=src)
+    assert (ref_idx >= 0).sum() > 200
+    assert np.array_equal(idx[src][~amb], ref_idx[~amb])
+    print(f"million-shape bounce S = {S}: max |dt| {err:.2e}, max |t_ind| {ind.max():.3f}, "
+          f"{int(amb.sum())} ambiguous index rays of {amb.size}")
+
+
+def test_bounce_coincident_hits_progress(prt, oracle_mod):
+    """300 coincident faint splats in front of a few sources: every ray
+    through them lists 300 hits at the same peak depth, more than its hit
+    list holds, and the list's mean depth equals every listed depth.  The
+    compaction must still keep the nearest hit, so each round blends one
+    and the walk ends (no round cap, no flag), matching the oracle."""
+    rng = np.random.default_rng(51)
+    m = 300
+    cluster = dict(means=np.tile([0.0, 0.0, 1.0], (m, 1)), quats=np.tile([1.0, 0.0, 0.0, 0.0], (m, 1)),
+                   log_scales=np.full((m, 3), np.log(0.12)), opacity=np.full(m, 0.004),
+                   normals=np.tile([0.0, 0.0, -1.0], (m, 1)), albedo=np.full((m, 3), 0.6))
+    k = 4
+    srcs = dict(means=np.column_stack([rng.uniform(-0.05, 0.05, (k, 2)), np.zeros(k)]),
+                quats=np.tile([1.0, 0.0, 0.0, 0.0], (k, 1)), log_scales=np.full((k, 3), np.log(0.01)),
+                opacity=np.full(k, 0.5), normals=np.tile([0.0, 0.0, 1.0], (k, 1)), albedo=np.full((k, 3), 0.5))
+    scene = as_f32(scenegen._concat([srcs, cluster]))
+    S = 256
+    params = prt.TransferParams(num_dirs=S, sh_bands=3, bounces=1)
+    sc = prt.Scene.from_arrays(scene)
+    bvh = prt.build_bvh(sc, check=True)
+    t = prt.precompute_transfer(sc, bvh, params, check=True).cpu().numpy()
+    st = prt.traversal_stats(sc, bvh, params)
+    assert st["rounds"] > st["traced_rays"] + 10       # the lists overflowed and were compacted
+    ref = oracle_mod.full_transfer(scene, S, 3, 1, sources=np.arange(k), want_allow=True)
+    assert np.abs(ref["t_ind"]).max() > 1e-2
+    assert_transfer_parity(t[:k], ref["t"], ref["allow"], what="coincident bounce")
 
 
 def _rot(q):

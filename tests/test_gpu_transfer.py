@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import scenegen
-from helpers import as_f32, assert_transfer_parity
+from helpers import as_f32, assert_ray_vis, assert_transfer_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -140,14 +140,11 @@ def test_transfer_cloud1k_full(prt, oracle_mod):
     scene = as_f32(w["scene"])
     params = prt.TransferParams(num_dirs=64, sh_bands=3)
     _, _, (t, vis) = _run(prt, scene, params, want_vis=True)
-    ref = oracle_mod.direct_transfer(scene, 64, 3, want_vis=True, want_allow=True)
+    ref = oracle_mod.direct_transfer(scene, 64, 3, want_vis=True, want_allow=True, want_vis_bounds=True)
     err = assert_transfer_parity(t.cpu().numpy()[:, 0, :], ref["t"], ref["allow"])
-    v = vis.cpu().numpy()
-    assert np.array_equal(v == -1, ref["vis"] == -1)        # the same rays are traced
-    traced = ref["vis"] != -1
-    dv = np.abs(v - ref["vis"])[traced]
-    assert (dv > 1e-5).mean() < 2e-3
-    print(f"cloud1k max |dt| = {err:.2e}, rays with |dV| > 1e-5: {(dv > 1e-5).sum()} of {dv.size}")
+    cos = scene["normals"] @ oracle_mod.directions(64).T
+    rays, wide = assert_ray_vis(vis.cpu().numpy(), ref, cos, oracle_mod.DEFAULT_MARGINS[0], "cloud1k")
+    print(f"cloud1k max |dt| = {err:.2e}; {rays} rays within their range, {wide} of them near a threshold")
 
 
 @pytest.mark.parametrize("bands,S", [(1, 16), (2, 32), (4, 64)])

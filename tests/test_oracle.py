@@ -313,6 +313,44 @@ def test_allowance_covers_threshold_perturbations(oracle_mod):
     assert np.median(base["allow"]) < 1e-2 * np.abs(base["t"]).max()
 
 
+def test_allowance_covers_t_min_and_hemisphere_perturbations(oracle_mod):
+    """The same for the two other predicates: moving t_min (the peak-depth
+    cut, where same-surface neighbours of a source sit) and the hemisphere
+    threshold of c = n . w inside wide margins changes every ray's V by no more
+    than its [vis_lo, vis_hi] range, a ray's traced status only where its
+    hemisphere test is ambiguous, and the direct and bounce transfers by no
+    more than the deviation bound."""
+    sc = scenegen.surface_scene(900, 33)
+    margins = (2e-3, 5e-5, 0.5, 1e-4, 1e-5)   # t margin >= 0.5 s_min >= 2.5e-4
+    src = np.arange(0, 900, 9)
+    S = 64
+    base = oracle_mod.direct_transfer(sc, S, 3, sources=src, want_vis=True, want_allow=True,
+                                      want_vis_bounds=True, margins=margins)
+    full = oracle_mod.full_transfer(sc, S, 3, 1, sources=src, want_allow=True, margins=margins)
+    dirs = oracle_mod.directions(S)
+    amb_c = np.abs(sc["normals"][src] @ dirs.T) <= margins[0]
+    moved_t = moved_c = 0
+    for cut in (dict(t_min=1e-4), dict(t_min=-1e-4), dict(c_min=1e-3), dict(c_min=-1e-3)):
+        var = oracle_mod.direct_transfer(sc, S, 3, sources=src, cut=cut, want_vis=True)
+        v0, v1 = base["vis"], var["vis"]
+        flip = (v0 == -1) != (v1 == -1)
+        assert not (flip & ~amb_c).any(), cut
+        both = (v0 != -1) & (v1 != -1)
+        assert (v1[both] >= base["vis_lo"][both] - 1e-12).all() and (v1[both] <= base["vis_hi"][both] + 1e-12).all()
+        diff = np.abs(var["t"] - base["t"])
+        assert (diff <= base["allow"] + 1e-12).all(), (cut, (diff - base["allow"]).max())
+        fv = oracle_mod.full_transfer(sc, S, 3, 1, sources=src, cut=cut, margins=margins)
+        fdiff = np.abs(fv["t"] - full["t"])
+        assert (fdiff <= full["allow"] + 1e-12).all(), (cut, (fdiff - full["allow"]).max())
+        if "t_min" in cut:
+            moved_t += int((np.abs(v1[both] - v0[both]) > 1e-12).sum())
+        else:
+            moved_c += int(flip.sum())
+    # the perturbations reach real rays: same-surface neighbours whose peak
+    # lies within 1e-4 of the origin, and rays within 1e-3 of the horizon
+    assert moved_t > 0 and moved_c > 0, (moved_t, moved_c)
+
+
 def test_bounce_partition_of_unity(oracle_mod):
     """With t_dir = e_0 for every hit and rho = pi, the bounce term of a ray
     is c (sum_j alpha_j T_j) = c (1 - T_end) (telescoping)."""

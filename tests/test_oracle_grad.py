@@ -107,9 +107,10 @@ def test_relight_grads_by_finite_differences(oracle_mod):
 
 
 def test_per_gaussian_gradient_matches_autograd(oracle_mod):
-    """The per-ray gradient of one Gaussian's opacity, scales, rotation and
-    normal equals the full autograd gradient (both FP64, independent
-    routes: per-ray visibilities from the C forward vs the torch graph)."""
+    """The per-ray gradient of one Gaussian's opacity, scales, rotation, mean
+    (as occluder and as the origin of its own rays) and normal equals the
+    full autograd gradient (both FP64, independent routes: per-ray
+    visibilities from the C forward vs the torch graph)."""
     from oracle.grad import gaussian_param_grads, loss_and_grads
     sc = scenegen.random_cloud(120, 41)
     sc["means"] *= 0.3
@@ -120,8 +121,8 @@ def test_per_gaussian_gradient_matches_autograd(oracle_mod):
     dT = np.einsum("nbc,bck->nk", C - target, np.asarray(light, dtype=np.float64))
     for j in (0, 7, 33, 90):
         got = gaussian_param_grads(sc, j, 48, 3, dT)
-        assert got["rays"] > 0
-        for key in ("opacity", "log_scales", "quats", "normals"):
+        assert got["rays"] > 0 and got["own_hits"] > 0
+        for key in ("opacity", "log_scales", "quats", "means", "normals"):
             r = np.asarray(ref["grads"][key][j], dtype=np.float64)
             g = np.asarray(got["grads"][key], dtype=np.float64)
             assert np.abs(g - r).max() <= 1e-9 * (1.0 + np.abs(r).max()), (j, key, g, r)
