@@ -361,13 +361,13 @@ def time_steps(prt, torch, np, sc, params, light, steps, warmup):
     for _ in range(warmup):
         step(False)
     torch.cuda.synchronize()
-    prt.check_flags(ws_tr.buf, "transfer")
     timer.marks.clear()
     t0 = time.perf_counter()
     for _ in range(steps):
         step(True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    prt.check_flags(ws_tr.buf, "transfer")
     return {"ms_step": wall * 1e3 / steps, "build": float(np.mean(timer.ms("build"))),
             "transfer": float(np.mean(timer.ms("transfer"))), "relight": float(np.mean(timer.ms("relight"))),
             "transfer_all": timer.ms("transfer"), "bvh": holder["bvh"], "transfer_out": transfer}
