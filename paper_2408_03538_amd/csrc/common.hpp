@@ -148,10 +148,10 @@ struct TransferArgs {
     const float* albedo;    // [n][3] original order (bounce)
     float4* albedo_sorted;  // [n] leaf order (bounce scratch), or null
     uint64_t* hitkey;       // bounce: per-lane hit lists of the persistent waves,
-    float* hitalpha;        // [wave][kHitList][64] keys (t bits, leaf rank) and alphas
+    float* hitalpha;        // [wave][64][kHitList] keys (t bits, leaf rank) and alphas
     float* partial;         // blend: [kBlendPartsMax][n][3][K] each direction part's
                             // bounce sums, added into transfer in part order
-    int2* hitrec;           // blend: [wave][kHitList][64] (leaf rank, weight) of the
+    int2* hitrec;           // blend: [wave][64][kHitList] (leaf rank, weight) of the
                             // hits blended in the current round, in blend order
     unsigned* queue;        // bounce: work counter (zeroed before the launch)
     float* rayw;            // [S][count] direction-order position: T c of each

@@ -316,9 +316,13 @@ __device__ inline int key_j(uint64_t k) { return (int)(uint32_t)k; }
 // transmittance below T_eps.  The traversal appends every hit beyond the last
 // blended one and no farther than the depth the direct pass needed to a list
 // of the lane's own in device memory, unsorted (the traversal meets them in
-// no useful order).  Afterwards the lane blends the list nearest first,
-// kBlend hits at a time: one pass over the list (coalesced across the wave)
-// keeps the kBlend nearest unblended keys in a sorted register buffer
+// no useful order), contiguous per lane so that its appends fill whole cache
+// lines (interleaving the lanes' entries instead left lines part-written
+// when evicted: 3.6x the appended bytes were written back, and the million-
+// splat bounce took 2.65 s against 2.41 s).  Afterwards the lane blends the
+// list nearest first, kBlend hits at a time: one pass over the list (each
+// lane reading its own entries in order) keeps the kBlend nearest unblended
+// keys in a sorted register buffer
 // (merge_chunk folds in kScan entries at a time), and
 // each blended hit's weight goes to a per-lane record list; the records are
 // summed into the transfer once the round's selection is over, so that the
@@ -396,9 +400,10 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
     // the grid is whole blocks: a wave past the lists' capacity has none and
     // leaves before it takes work (no block-wide barrier follows)
     if (wslot >= bounce_waves(a.n, kIndex)) return;
-    uint64_t* const lkey = a.hitkey + (size_t)wslot * M * kWave + lane;   // entry q at [q * kWave]
-    float* const lalpha = a.hitalpha + (size_t)wslot * M * kWave + lane;
-    int2* const lrec = kIndex ? nullptr : a.hitrec + (size_t)wslot * M * kWave + lane;
+    // each lane's list is contiguous (entry q at [q]): a lane's appends fill whole cache lines
+    uint64_t* const lkey = a.hitkey + (size_t)wslot * M * kWave + (size_t)lane * M;
+    float* const lalpha = a.hitalpha + (size_t)wslot * M * kWave + (size_t)lane * M;
+    int2* const lrec = kIndex ? nullptr : a.hitrec + (size_t)wslot * M * kWave + (size_t)lane * M;
     const int groups = (a.count + G - 1) / G;
     const HitParams hp = a.hp;
     RayCounts rc;   // (kCount) single-ray traversal work, hits blended and listed, rounds
@@ -483,7 +488,7 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                 auto compact = [&]() {
                     uint64_t kmin = kNoHit;   // every listed key is below k_over
                     for (int q = 0; q < cnt; ++q) {
-                        const uint64_t k = lkey[q * kWave];
+                        const uint64_t k = lkey[q];
                         kmin = k < kmin ? k : kmin;
                     }
                     uint64_t pivot = hit_key(sum_t / (float)cnt, 0);
@@ -494,11 +499,11 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                     uint64_t kmax = 0;
                     int imax = 0;
                     for (int q = 0; q < cnt; ++q) {
-                        const uint64_t k = lkey[q * kWave];
-                        const float al = lalpha[q * kWave];
+                        const uint64_t k = lkey[q];
+                        const float al = lalpha[q];
                         if (k < k_over) {
-                            lkey[kept * kWave] = k;
-                            lalpha[kept * kWave] = al;
+                            lkey[kept] = k;
+                            lalpha[kept] = al;
                             if (k > kmax) {
                                 kmax = k;
                                 imax = kept;
@@ -511,8 +516,8 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                         k_over = kmax;
                         kept_sum -= key_t(kmax);
                         --kept;
-                        lkey[imax * kWave] = lkey[kept * kWave];
-                        lalpha[imax * kWave] = lalpha[kept * kWave];
+                        lkey[imax] = lkey[kept];
+                        lalpha[imax] = lalpha[kept];
                     }
                     cnt = kept;
                     sum_t = kept_sum;
@@ -540,8 +545,8 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                         }
                         if (cnt == M) compact();
                         if (key < k_over) {
-                            lkey[cnt * kWave] = key;
-                            lalpha[cnt * kWave] = h.alpha;
+                            lkey[cnt] = key;
+                            lalpha[cnt] = h.alpha;
                             sum_t += h.t;
                             ++cnt;
                         }
@@ -571,8 +576,8 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                         for (int u = 0; u < kScan; ++u) {
                             const int q = q0 + u;
                             const bool inl = more && q < cnt;
-                            kk[u] = inl ? lkey[q * kWave] : kNoHit;
-                            aa[u] = inl ? lalpha[q * kWave] : 0.0f;
+                            kk[u] = inl ? lkey[q] : kNoHit;
+                            aa[u] = inl ? lalpha[q] : 0.0f;
                         }
                         bool anysel = false;
 #pragma unroll
@@ -611,7 +616,7 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                             if (T < hp.T_eps || T <= bestW) done = true;
                         } else if (!kIndex && more && !done && bk[q] != kNoHit) {
                             // the hit's weight, summed into the transfer after the selection
-                            lrec[nrec * kWave] = make_int2(key_j(bk[q]), __float_as_int(ba[q] * T * wc));
+                            lrec[nrec] = make_int2(key_j(bk[q]), __float_as_int(ba[q] * T * wc));
                             ++nrec;
                             T *= 1.0f - ba[q];
                             k_last = bk[q];
@@ -637,7 +642,7 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
 #pragma unroll
                         for (int k = 0; k < K; ++k) acc[ch][k] = 0.0f;
                     for (int q = 0; q < nrec; ++q) {
-                        const int2 e = lrec[q * kWave];
+                        const int2 e = lrec[q];
                         const int r = e.x;
                         const float w = __int_as_float(e.y);
                         const float4 rho = a.albedo_sorted[r];
