@@ -569,7 +569,9 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                         ba[q] = 0.0f;
                     }
                     for (int q0 = 0; q0 < maxcnt; q0 += kScan) {
-                        // kScan entries' loads in flight together
+                        // kScan keys' loads in flight together; the buffer carries
+                        // each key's list position (bits in a float), and only the
+                        // selected entries' alphas are read, after the pass
                         uint64_t kk[kScan];
                         float aa[kScan];
 #pragma unroll
@@ -577,7 +579,7 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                             const int q = q0 + u;
                             const bool inl = more && q < cnt;
                             kk[u] = inl ? lkey[q] : kNoHit;
-                            aa[u] = inl ? lalpha[q] : 0.0f;
+                            aa[u] = __int_as_float(q);
                         }
                         bool anysel = false;
 #pragma unroll
@@ -590,6 +592,10 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                         }
                         if (__ballot(anysel) != 0ull) merge_chunk<kScan>(kk, aa, bk, ba);
                     }
+                    // the selected entries' alphas (their loads in flight together)
+#pragma unroll
+                    for (int q = 0; q < kBlend; ++q)
+                        ba[q] = (more && bk[q] != kNoHit) ? lalpha[__float_as_int(ba[q])] : 0.0f;
                     int got = 0;
 #pragma unroll
                     for (int q = 0; q < kBlend; ++q) {
