@@ -333,7 +333,8 @@ __device__ inline int key_j(uint64_t k) { return (int)(uint32_t)k; }
 // still transparent, traverses again from its last hit.  The launch is
 // persistent: a fixed set of waves takes groups of sources from a counter,
 // so the lists are sized by the waves, not the scene.
-constexpr int kBlend = 8;   // hits selected per pass over the list
+constexpr int kSelBlend = 16;   // hits selected per pass over the list: the blend
+constexpr int kSelIndex = 8;    // and the index walk
 constexpr int kCheck = 8;   // depth checkpoints per ray and round
 
 // Compare-exchange of two (key, alpha) pairs: the smaller key ends in a.
@@ -349,16 +350,16 @@ __device__ inline void cas_pair(uint64_t& ka, float& aa, uint64_t& kb, float& ab
 }
 
 // Folds a chunk of N keys (ineligible ones set to kNoHit) into the sorted
-// buffer of the kBlend = 8 smallest: a sorting network orders the chunk
-// (Batcher's odd-even merge sort), the buffer followed by the chunk reversed
-// is bitonic, so one half-cleaner step leaves the 8 smallest of both in the
-// buffer, and the bitonic merge network sorts them.  34 VALU per entry at
-// N = 8 against 56 for an insertion into the buffer, which one lane or
-// another needs at almost every entry.
-template <int N>
-__device__ inline void merge_chunk(uint64_t (&kk)[N], float (&aa)[N], uint64_t (&bk)[kBlend], float (&ba)[kBlend])
+// buffer of the B smallest: a sorting network orders the chunk (Batcher's
+// odd-even merge sort), the buffer followed by the chunk reversed is
+// bitonic, so one half-cleaner step leaves the B smallest of both in the
+// buffer, and the bitonic merge network sorts them.  At B = 8, N = 8 that is
+// 34 VALU per entry against 56 for an insertion into the buffer, which one
+// lane or another needs at almost every entry.
+template <int N, int B>
+__device__ inline void merge_chunk(uint64_t (&kk)[N], float (&aa)[N], uint64_t (&bk)[B], float (&ba)[B])
 {
-    static_assert(kBlend == 8 && (N == 4 || N == 8), "networks for 4 or 8 entries into 8");
+    static_assert((B == 8 || B == 16) && (N == 4 || N == 8), "networks for 4 or 8 entries into 8 or 16");
     auto c = [&](int i, int j) { cas_pair(kk[i], aa[i], kk[j], aa[j]); };
     if constexpr (N == 4) {
         c(0, 1); c(2, 3); c(0, 2); c(1, 3); c(1, 2);
@@ -371,15 +372,17 @@ __device__ inline void merge_chunk(uint64_t (&kk)[N], float (&aa)[N], uint64_t (
         c(1, 2); c(3, 4); c(5, 6);
     }
 #pragma unroll
-    for (int q = kBlend - N; q < kBlend; ++q) {
-        const bool lt = kk[kBlend - 1 - q] < bk[q];
-        bk[q] = lt ? kk[kBlend - 1 - q] : bk[q];
-        ba[q] = lt ? aa[kBlend - 1 - q] : ba[q];
+    for (int q = B - N; q < B; ++q) {
+        const bool lt = kk[B - 1 - q] < bk[q];
+        bk[q] = lt ? kk[B - 1 - q] : bk[q];
+        ba[q] = lt ? aa[B - 1 - q] : ba[q];
     }
-    auto b = [&](int i, int j) { cas_pair(bk[i], ba[i], bk[j], ba[j]); };
-    b(0, 4); b(1, 5); b(2, 6); b(3, 7);
-    b(0, 2); b(1, 3); b(4, 6); b(5, 7);
-    b(0, 1); b(2, 3); b(4, 5); b(6, 7);
+    // bitonic merge of the B-entry buffer: half-cleaners at distance B/2, ..., 1
+#pragma unroll
+    for (int dist = B / 2; dist >= 1; dist >>= 1)
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            if ((i & dist) == 0) cas_pair(bk[i], ba[i], bk[i + dist], ba[i + dist]);
 }
 
 // kIndex: the paper's own bounce instead of the blend -- the same walk, but
@@ -393,6 +396,7 @@ template <int K, bool kIndex, int kScan, bool kCount = false>
 __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long long* stats = nullptr)
 {
     constexpr int M = kHitList;
+    constexpr int kBlend = kIndex ? kSelIndex : kSelBlend;
     const int lane = threadIdx.x & (kWave - 1);
     const int G = a.G;
     const int D = kWave / G;
@@ -590,7 +594,7 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                             kk[u] = sel ? k : kNoHit;
                             anysel |= sel;
                         }
-                        if (__ballot(anysel) != 0ull) merge_chunk<kScan>(kk, aa, bk, ba);
+                        if (__ballot(anysel) != 0ull) merge_chunk<kScan, kBlend>(kk, aa, bk, ba);
                     }
                     // the selected entries' alphas (their loads in flight together)
 #pragma unroll
@@ -705,14 +709,16 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
 }
 
 // The two modes hold different registers at their peak (the blend its 3K
-// sums, the index mode none), so each gets the occupancy and scan width that
-// measured fastest: the blend 4 waves per SIMD and 8 entries per step, the
-// index walk 5 waves and 4 entries (a few cold spills in both).
+// sums, the index mode none), so each gets the occupancy, buffer and scan
+// width that measured fastest: the blend 4 waves per SIMD, a 16-hit buffer
+// and 4 entries per step (fewer passes over the lists than with 8 hits: the
+// million-splat transfer call 3.34 -> 3.29 s), the index walk 5 waves, 8
+// hits and 4 entries (a few cold spills in both).
 template <int K>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceWavesPerSimd))) void bounce_kernel(
     TransferArgs a)
 {
-    bounce_walk<K, false, 8>(a);
+    bounce_walk<K, false, 4>(a);
 }
 template <int K>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kIndexWavesPerSimd))) void index_kernel(
@@ -725,7 +731,7 @@ template <int K>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceWavesPerSimd))) void bounce_count_kernel(
     TransferArgs a, unsigned long long* stats)
 {
-    bounce_walk<K, false, 8, true>(a, stats);
+    bounce_walk<K, false, 4, true>(a, stats);
 }
 
 // ---------------------------------------------------------------------------
