@@ -79,25 +79,29 @@ __global__ __launch_bounds__(kThreadsF32) void relight_f32_kernel(int n, const f
 }
 
 // ------------------------------------------------------------------ MFMA path
-// GEMM of 16-splat row tiles against 16-column tiles of outputs (b, c) with
-// v_mfma_f32_16x16x32_{bf16,f16}.  The 32-deep contraction of one MFMA is
-// [T_c' | T_c'] . [L_hi ; L_lo] for channel c', where L_hi is the light
+// GEMM of 16-column tiles of outputs (b, c) against 16-splat row tiles with
+// v_mfma_f32_16x16x32_{bf16,f16}, computed transposed: D = L' T'^T, so that
+// lane l ends with D[4 (l / 16) + 0..3][l % 16] = colour[row l % 16][four
+// consecutive columns] and writes them at once (8 bytes as 16-bit colours,
+// 16 as FP32) into a wave-private LDS patch, from which each chunk of CT
+// column tiles leaves in 16-byte stores of whole row pieces (each row of a
+// chunk is contiguous in memory).  The 32-deep contraction of one MFMA is
+// [L_hi ; L_lo] against [T_c' | T_c'] for channel c', where L_hi is the light
 // rounded to 16 bits and L_lo the rounded remainder, so the light enters at
 // ~FP32 precision; columns of other channels get zeros (C == 3 needs C such
-// steps).  Lane l holds A[l % 16][8 (l / 16) + 0..7], B[8 (l / 16) + 0..7][l % 16]
-// and D[4 (l / 16) + 0..3][l % 16].
+// steps).  Lane l holds A[l % 16][8 (l / 16) + 0..7] (light, column l % 16)
+// and B[8 (l / 16) + 0..7][l % 16] (transfer, row l % 16).
 // Work item = one 16-row tile against a group of up to kGroupTiles column
 // tiles (192 output columns: every light of a 64-light batch), so each
-// transfer row is read once per group.  The block builds the B fragments of
-// its group once, in LDS; each wave then walks row tiles on its own (no
-// block barrier after the set-up), loading its A fragments once per tile and
-// producing the group's columns in chunks of CT tiles.  Each chunk's result
-// goes through a wave-private LDS patch so that its 16 rows x 16 CT columns
-// leave in 16-byte stores (each row of a chunk is contiguous in memory).
+// transfer row is read once per group.  The block builds the light
+// fragments of its group once, in LDS; each wave then walks row tiles on its
+// own (no block barrier after the set-up), loading its transfer fragments
+// once per tile and producing the group's columns in chunks.
 
-// waves per block: 4 with 16-bit colours, 8 with FP32 colours (measured)
+// waves per block: 8 (the 3M x 64-light relight with 16-bit colours at 4
+// waves took 0.32 ms, at 8 waves 0.29 ms)
 template <bool OUT16>
-constexpr int waves_mfma() { return OUT16 ? 4 : 8; }
+constexpr int waves_mfma() { return 8; }
 constexpr int kChunkTiles = 4;   // column tiles per chunk (64 output columns)
 constexpr int kGroupTiles = 12;  // column tiles per group (3 chunks)
 
@@ -118,6 +122,13 @@ struct Frag<false> {
     static __device__ inline elem from_float(float x) { return (elem)x; }
 };
 
+// IEEE binary16 bits of x, rounded to nearest even.
+__device__ inline uint32_t half_bits(float x)
+{
+    const _Float16 h = (_Float16)x;
+    return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+
 template <int K, int C, bool BF, bool OUT16>
 __global__ __launch_bounds__(waves_mfma<OUT16>() * kWave) void relight_mfma_kernel(int n, const void* __restrict__ Tv, int B,
                                                                           const float* __restrict__ L,
@@ -126,22 +137,23 @@ __global__ __launch_bounds__(waves_mfma<OUT16>() * kWave) void relight_mfma_kern
     using F = Frag<BF>;
     using vec = typename F::vec;
     using elem = typename F::elem;
-    constexpr int CT = kChunkTiles;
     constexpr int kWavesMfma = waves_mfma<OUT16>();
     constexpr int kOutBytes = OUT16 ? 2 : 4;
-    constexpr int kRowBytes = CT * 16 * kOutBytes;          // one row of a chunk: 128 or 256 B
-    __shared__ vec bsh[kGroupTiles][C][kWave];
-    __shared__ __align__(16) unsigned char stage[kWavesMfma][16 * kRowBytes];
+    constexpr int CT = kChunkTiles;
+    constexpr int kRowBytes = CT * 16 * kOutBytes;   // one row of a chunk: 128 or 256 B
+    constexpr int kPatchStride = kRowBytes + 16;     // padded: the 16 rows fall in different banks
+    __shared__ vec lsh[kGroupTiles][C][kWave];
+    __shared__ __align__(16) unsigned char stage[kWavesMfma][16 * kPatchStride];
     const elem* T = static_cast<const elem*>(Tv);
     const int lane = threadIdx.x & (kWave - 1);
     const int wslot = threadIdx.x / kWave;
-    const int g = lane / 16;   // k group of the lane's A/B fragment
-    const int li = lane % 16;  // row (A) / column (B, D) of the lane
+    const int g = lane / 16;   // k group of the lane's fragments; its 4 output columns 4g..4g+3
+    const int li = lane % 16;  // column (light fragment) / row (transfer fragment, output) of the lane
     const int cols = 3 * B;
     const int group_col0 = blockIdx.y * kGroupTiles * 16;
     const int group_tiles = min(kGroupTiles, (cols - group_col0 + 15) / 16);
 
-    // B fragments of the group's column tiles (wave w builds tiles w, w + 4, ...)
+    // light fragments of the group's column tiles (wave w builds tiles w, w + waves, ...)
     for (int m = wslot; m < group_tiles; m += kWavesMfma) {
         const int col = group_col0 + m * 16 + li;
         const bool cvalid = col < cols;
@@ -161,7 +173,7 @@ __global__ __launch_bounds__(waves_mfma<OUT16>() * kWave) void relight_mfma_kern
                 }
                 v[e] = F::from_float(x);
             }
-            bsh[m][st][lane] = v;
+            lsh[m][st][lane] = v;
         }
     }
     __syncthreads();
@@ -172,11 +184,11 @@ __global__ __launch_bounds__(waves_mfma<OUT16>() * kWave) void relight_mfma_kern
     for (int rt = blockIdx.x * kWavesMfma + wslot; rt < ntiles_rows; rt += gridDim.x * kWavesMfma) {
         const int64_t row = (int64_t)rt * 16 + li;
         const bool rvalid = row < n;
-        vec afrag[C];
+        vec tfrag[C];
 #pragma unroll
         for (int st = 0; st < C; ++st) {
             if (K == 16 && rvalid) {
-                afrag[st] = *reinterpret_cast<const vec*>(T + ((size_t)row * C + st) * 16 + 8 * (g & 1));
+                tfrag[st] = *reinterpret_cast<const vec*>(T + ((size_t)row * C + st) * 16 + 8 * (g & 1));
             } else {
                 vec v;
 #pragma unroll
@@ -184,7 +196,7 @@ __global__ __launch_bounds__(waves_mfma<OUT16>() * kWave) void relight_mfma_kern
                     const int kk = (8 * g + e) & 15;
                     v[e] = (rvalid && kk < K) ? T[((size_t)row * C + st) * K + kk] : F::from_float(0.0f);
                 }
-                afrag[st] = v;
+                tfrag[st] = v;
             }
         }
         const int nrows = (int)min((int64_t)16, (int64_t)n - (int64_t)rt * 16);
@@ -196,14 +208,13 @@ __global__ __launch_bounds__(waves_mfma<OUT16>() * kWave) void relight_mfma_kern
                 if (m0 + m < group_tiles) {
                     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                    for (int st = 0; st < C; ++st) acc = F::mma(afrag[st], bsh[m0 + m][st][lane], acc);
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int r = 4 * g + v;
-                        const int c = m * 16 + li;
-                        if (OUT16) reinterpret_cast<__half*>(my_stage)[r * CT * 16 + c] = __float2half(acc[v]);
-                        else reinterpret_cast<float*>(my_stage)[r * CT * 16 + c] = acc[v];
-                    }
+                    for (int st = 0; st < C; ++st) acc = F::mma(lsh[m0 + m][st][lane], tfrag[st], acc);
+                    unsigned char* at = my_stage + li * kPatchStride + (m * 16 + 4 * g) * kOutBytes;
+                    if (OUT16)
+                        *reinterpret_cast<uint2*>(at) = make_uint2(half_bits(acc[0]) | (half_bits(acc[1]) << 16),
+                                                                   half_bits(acc[2]) | (half_bits(acc[3]) << 16));
+                    else
+                        *reinterpret_cast<float4*>(at) = make_float4(acc[0], acc[1], acc[2], acc[3]);
                 }
             }
             __builtin_amdgcn_wave_barrier();
@@ -220,18 +231,18 @@ __global__ __launch_bounds__(waves_mfma<OUT16>() * kWave) void relight_mfma_kern
                     const int r = pc / kPiecesPerRow, piece = pc % kPiecesPerRow;
                     if (r < nrows)
                         *reinterpret_cast<uint4*>(obase + r * row_stride + piece * 16) =
-                            *reinterpret_cast<const uint4*>(my_stage + r * kRowBytes + piece * 16);
+                            *reinterpret_cast<const uint4*>(my_stage + r * kPatchStride + piece * 16);
                 }
             } else {
                 for (int e = lane; e < 16 * chunk_cols; e += kWave) {
                     const int r = e / chunk_cols, c = e % chunk_cols;
                     if (r < nrows) {
                         if (OUT16)
-                            reinterpret_cast<__half*>(obase + r * row_stride)[c] =
-                                reinterpret_cast<const __half*>(my_stage)[r * CT * 16 + c];
+                            reinterpret_cast<uint16_t*>(obase + r * row_stride)[c] =
+                                reinterpret_cast<const uint16_t*>(my_stage + r * kPatchStride)[c];
                         else
                             reinterpret_cast<float*>(obase + r * row_stride)[c] =
-                                reinterpret_cast<const float*>(my_stage)[r * CT * 16 + c];
+                                reinterpret_cast<const float*>(my_stage + r * kPatchStride)[c];
                     }
                 }
             }
