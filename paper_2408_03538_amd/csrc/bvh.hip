@@ -1,16 +1,14 @@
 // Linear BVH over the Gaussians' 3-sigma boxes (the Gaussian ray tracer of
 // Sec. 4.4 is built on a BVH): scene bounds -> 30-bit Morton codes of the
-// centres -> stable LSD radix sort -> per-leaf ray-test records (Eq. 1-2) ->
+// centres -> stable LSD radix sort (sort.hpp) -> per-leaf ray-test records (Eq. 1-2) ->
 // Karras hierarchy -> bottom-up refit of the child boxes.
 #include "common.hpp"
+#include "sort.hpp"
 
 namespace prtgs {
 
 namespace {
 
-constexpr int kSortBlock = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kReduceBlock = 256;
 
 struct BuildWs {
@@ -20,7 +18,6 @@ struct BuildWs {
 BuildWs build_ws_layout(int n)
 {
     BuildWs w;
-    size_t nb = (size_t)((n + kSortTile - 1) / kSortTile);
     size_t nr = (size_t)((n + kReduceBlock - 1) / kReduceBlock);
     size_t off = kFlagBytes;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
@@ -28,7 +25,7 @@ BuildWs build_ws_layout(int n)
     w.vals0 = take(4 * (size_t)n);
     w.keys1 = take(4 * (size_t)n);
     w.vals1 = take(4 * (size_t)n);
-    w.hist = take(4 * 256 * nb);
+    w.hist = take(sortk::sort_scratch_bytes(n));
     w.leafbox = take(24 * (size_t)n);
     w.ibox = take(24 * (size_t)(n > 1 ? n - 1 : 1));
     w.parent_int = take(4 * (size_t)(n > 1 ? n - 1 : 1));
@@ -135,99 +132,6 @@ __global__ void morton_kernel(const float* __restrict__ means, int n, const BvhH
     }
     keys[i] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
     vals[i] = i;
-}
-
-// ---------------------------------------------------------------- radix sort
-// Stable LSD sort of (key, value) pairs by 8-bit digits.  Per pass: tile
-// histograms in digit-major order, one exclusive scan over them (giving each
-// tile's output base per digit), then a stable scatter in which lanes of one
-// wave find equal digits by bitwise ballots.
-
-__global__ void radix_hist_kernel(const uint32_t* __restrict__ keys, int n, int shift, uint32_t* __restrict__ hist,
-                                  int ntiles)
-{
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    size_t base = (size_t)blockIdx.x * kSortTile;
-    for (int it = 0; it < kSortItems; ++it) {
-        size_t i = base + (size_t)it * kSortBlock + threadIdx.x;
-        if (i < (size_t)n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    hist[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
-}
-
-constexpr int kScanBlock = 1024;
-
-__global__ void exclusive_scan_kernel(uint32_t* __restrict__ data, int count)
-{
-    __shared__ uint32_t sums[kScanBlock];
-    int per = (count + kScanBlock - 1) / kScanBlock;
-    int beg = threadIdx.x * per;
-    int end = min(beg + per, count);
-    uint32_t local = 0;
-    for (int i = beg; i < end; ++i) local += data[i];
-    sums[threadIdx.x] = local;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of the per-thread sums
-    for (int off = 1; off < kScanBlock; off <<= 1) {
-        uint32_t v = threadIdx.x >= (unsigned)off ? sums[threadIdx.x - off] : 0u;
-        __syncthreads();
-        sums[threadIdx.x] += v;
-        __syncthreads();
-    }
-    uint32_t run = sums[threadIdx.x] - local;
-    for (int i = beg; i < end; ++i) {
-        uint32_t v = data[i];
-        data[i] = run;
-        run += v;
-    }
-}
-
-__global__ void radix_scatter_kernel(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
-                                     uint32_t* __restrict__ kout, int32_t* __restrict__ vout, int n, int shift,
-                                     const uint32_t* __restrict__ offsets, int ntiles)
-{
-    constexpr int kWaves = kSortBlock / kWave;
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wcnt[kWaves][256];
-    const int tid = threadIdx.x;
-    const int wave = tid / kWave;
-    const int lane = tid % kWave;
-    run[tid] = offsets[(size_t)tid * ntiles + blockIdx.x];
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    size_t base = (size_t)blockIdx.x * kSortTile;
-    for (int it = 0; it < kSortItems; ++it) {
-        for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
-        __syncthreads();
-        size_t i = base + (size_t)it * kSortBlock + tid;
-        bool valid = i < (size_t)n;
-        uint32_t key = valid ? kin[i] : 0u;
-        int32_t val = valid ? vin[i] : 0;
-        uint32_t dig = (key >> shift) & 255u;
-        uint64_t same = __ballot(valid);
-        for (int bit = 0; bit < 8; ++bit) {
-            uint64_t ones = __ballot(valid && ((dig >> bit) & 1u));
-            same &= ((dig >> bit) & 1u) ? ones : ~ones;
-        }
-        uint32_t rank = (uint32_t)__popcll(same & lt_mask);
-        if (valid && rank == 0) wcnt[wave][dig] = (uint32_t)__popcll(same);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = run[dig] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][dig];
-            if (pos < (uint32_t)n) {
-                kout[pos] = key;
-                vout[pos] = val;
-            }
-        }
-        __syncthreads();
-        uint32_t add = 0;
-        for (int w = 0; w < kWaves; ++w) add += wcnt[w][tid];
-        run[tid] += add;
-        __syncthreads();
-    }
 }
 
 // ---------------------------------------------------------------- leaves
@@ -388,7 +292,7 @@ hipError_t launch_build_bvh(const prtgs_gaussians& g, void* bvh, void* ws, unsig
     int32_t* order_out = reinterpret_cast<int32_t*>(b + L.order);
     uint32_t* keys[2] = {reinterpret_cast<uint32_t*>(w + W.keys0), reinterpret_cast<uint32_t*>(w + W.keys1)};
     int32_t* vals[2] = {reinterpret_cast<int32_t*>(w + W.vals0), reinterpret_cast<int32_t*>(w + W.vals1)};
-    uint32_t* hist = reinterpret_cast<uint32_t*>(w + W.hist);
+    void* hist = w + W.hist;   // sort scratch
     float* leafbox = reinterpret_cast<float*>(w + W.leafbox);
     float* ibox = reinterpret_cast<float*>(w + W.ibox);
     int32_t* parent_int = reinterpret_cast<int32_t*>(w + W.parent_int);
@@ -404,18 +308,11 @@ hipError_t launch_build_bvh(const prtgs_gaussians& g, void* bvh, void* ws, unsig
     hipLaunchKernelGGL(morton_kernel, dim3(blocks), dim3(256), 0, stream, g.means, n, hdr, keys[0], vals[0]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
-    int ntiles = (n + kSortTile - 1) / kSortTile;
-    int cur = 0;
-    for (int pass = 0; pass < 4; ++pass) {
-        int shift = 8 * pass;
-        hipLaunchKernelGGL(radix_hist_kernel, dim3(ntiles), dim3(kSortBlock), 0, stream, keys[cur], n, shift, hist,
-                           ntiles);
-        hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(kScanBlock), 0, stream, hist, 256 * ntiles);
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3(ntiles), dim3(kSortBlock), 0, stream, keys[cur], vals[cur],
-                           keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, ntiles);
-        cur ^= 1;
-    }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    bool in_alt = false;
+    if ((e = sortk::radix_sort_pairs<uint32_t, int32_t>(keys[0], vals[0], keys[1], vals[1], n, 0, 32, hist, stream,
+                                                        &in_alt)) != hipSuccess)
+        return e;
+    const int cur = in_alt ? 1 : 0;
 
     hipLaunchKernelGGL(leaf_kernel, dim3(blocks), dim3(256), 0, stream, g, vals[cur], prims, normals, leafbox,
                        order_out, flags);

@@ -9,10 +9,8 @@
 // per tile with batches staged in LDS.
 #include <cstring>
 
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
-
 #include "common.hpp"
+#include "sort.hpp"
 
 namespace prtgs {
 
@@ -292,24 +290,9 @@ __global__ __launch_bounds__(kTilePixels) void splat_render_kernel(SplatCamera c
 
 }  // namespace
 
-size_t splat_sort_temp_bytes(int64_t max_instances)
-{
-    size_t bytes = 0;
-    uint64_t* k = nullptr;
-    uint32_t* v = nullptr;
-    if (rocprim::radix_sort_pairs(nullptr, bytes, k, k, v, v, (size_t)max_instances, 0, 64) != hipSuccess) return 0;
-    return bytes;
-}
+size_t splat_sort_temp_bytes(int64_t max_instances) { return sortk::sort_scratch_bytes(max_instances); }
 
-size_t splat_scan_temp_bytes(int n)
-{
-    size_t bytes = 0;
-    const uint32_t* c = nullptr;
-    uint64_t* o = nullptr;
-    if (rocprim::exclusive_scan(nullptr, bytes, c, o, (uint64_t)0, (size_t)n, rocprim::plus<uint64_t>()) != hipSuccess)
-        return 0;
-    return bytes;
-}
+size_t splat_scan_temp_bytes(int n) { return sortk::scan_scratch_bytes(n); }
 
 hipError_t launch_splat_front(int n, const SplatCamera& cam, const float* means, const float* quats,
                               const float* log_scales, const float* opacity, const SplatBuffers& b,
@@ -320,9 +303,7 @@ hipError_t launch_splat_front(int n, const SplatCamera& cam, const float* means,
                        opacity, b.uv, b.conic_o, b.depth, b.rect, b.count, b.flags);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t scan_bytes = b.scan_temp_bytes;
-    e = rocprim::exclusive_scan(b.scan_temp, scan_bytes, b.count, b.offset, (uint64_t)0, (size_t)n,
-                                rocprim::plus<uint64_t>(), stream);
+    e = sortk::exclusive_scan<uint32_t, uint64_t>(b.count, b.offset, n, b.scan_temp, stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(splat_total_kernel, dim3(1), dim3(64), 0, stream, n, b.offset, b.count, b.total);
     return hipGetLastError();
@@ -335,6 +316,8 @@ hipError_t launch_splat_back(int n, const SplatCamera& cam, int64_t instances, c
     const int ntiles = ntx * nty;
     hipError_t e = fill_u32(reinterpret_cast<uint32_t*>(b.ranges), 0u, 2 * (size_t)ntiles, stream);
     if (e != hipSuccess) return e;
+    const uint64_t* sorted_keys = b.keys;   // where the sort leaves the pairs
+    const uint32_t* sorted_vals = b.vals;
     if (instances > 0) {
         hipLaunchKernelGGL(splat_duplicate_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, n, cam, ntx, ntiles,
                            b.offset, b.count, b.rect, b.uv, b.conic_o, b.depth, b.keys, b.vals, b.max_instances);
@@ -343,17 +326,21 @@ hipError_t launch_splat_back(int n, const SplatCamera& cam, int64_t instances, c
         // enough key bits for every tile number and the past-the-end one
         unsigned tile_bits = 1;
         while ((1u << tile_bits) <= (unsigned)ntiles) ++tile_bits;
-        size_t sort_bytes = b.sort_temp_bytes;
-        e = rocprim::radix_sort_pairs(b.sort_temp, sort_bytes, b.keys, b.keys_alt, b.vals, b.vals_alt,
-                                      (size_t)instances, 0, 32 + tile_bits, stream);
+        bool in_alt = false;
+        e = sortk::radix_sort_pairs<uint64_t, uint32_t>(b.keys, b.vals, b.keys_alt, b.vals_alt, instances, 0,
+                                                        32 + (int)tile_bits, b.sort_temp, stream, &in_alt);
         if (e != hipSuccess) return e;
+        if (in_alt) {
+            sorted_keys = b.keys_alt;
+            sorted_vals = b.vals_alt;
+        }
         hipLaunchKernelGGL(splat_ranges_kernel, dim3((unsigned)((instances + 255) / 256)), dim3(256), 0, stream,
-                           instances, (uint32_t)ntiles, b.keys_alt, b.ranges);
+                           instances, (uint32_t)ntiles, sorted_keys, b.ranges);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(splat_render_kernel, dim3(ntiles), dim3(kTilePixels), 0, stream, cam, ntx, b.ranges,
-                       b.vals_alt, b.uv, b.conic_o, colours, stride, image, final_T);
+                       sorted_vals, b.uv, b.conic_o, colours, stride, image, final_T);
     return hipGetLastError();
 }
 

@@ -261,8 +261,9 @@ def test_grad200k_central_differences(prt, oracle_mod):
             [("means", (a,)) for a in range(3)] + [("normals", (a,)) for a in range(3)]
     results = []
     D = torch.from_numpy(dirs)
-    for j in rng.choice(n, 16, replace=False):
+    for q, j in enumerate(rng.choice(n, 16, replace=False)):
         j = int(j)
+        _say(f"grad200k FD: Gaussian {q + 1} of 16 (index {j})")
         # rays of other sources that reach j (FP64, every source)
         with torch.no_grad():
             R = _rotation(torch.from_numpy(scene["quats"][j][None]))[0]
