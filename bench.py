@@ -54,10 +54,10 @@ FLOPS_PER_PRIM_TEST = 70
 # profiles/direct_kernel_surface100k_sq_counters.md); bounce: bounce_kernel<16>
 # of the million-splat workload (profiles/bounce_kernel_million_counters.md).
 MEASURED = {
-    "direct_surface100k": {"sources_sha256_16": "b73aee930e48aeba", "bytes_per_launch": 7.272e9,
+    "direct_surface100k": {"sources_sha256_16": "014a201dfedefb11", "bytes_per_launch": 7.270e9,
                            "valu_instructions_per_launch": 1.1732e10},
-    "bounce_million": {"sources_sha256_16": "b73aee930e48aeba", "bytes_per_launch": 6.677e12,
-                       "valu_instructions_per_launch": 1.3339e12},
+    "bounce_million": {"sources_sha256_16": "014a201dfedefb11", "bytes_per_launch": 3.321e12,
+                       "valu_instructions_per_launch": 1.3217e12},
 }
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
                   "paper_2408_03538_amd/csrc/common.hpp", "paper_2408_03538_amd/csrc/capi.hip"]   # capi: work split
