@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PRTGS_ABI_VERSION 4   /* 4: explicit work split in prtgs_transfer_desc */
+#define PRTGS_ABI_VERSION 5   /* 5: one-walk blended bounce (bounce_records in prtgs_transfer_desc) */
 
 typedef enum {
     PRTGS_OK = 0,
@@ -53,6 +53,8 @@ typedef enum { PRTGS_F32 = 0, PRTGS_BF16 = 1, PRTGS_F16 = 2 } prtgs_dtype;
 #define PRTGS_FLAG_STACK_OVERFLOW 0x2u  /* BVH deeper than the traversal stack */
 #define PRTGS_FLAG_BAD_TREE 0x4u        /* malformed BVH (wrong buffer or n): traversal stopped */
 #define PRTGS_FLAG_BAD_INDEX 0x8u       /* an index-matrix entry outside [-1, n): skipped */
+#define PRTGS_FLAG_RECORDS_DEFERRED 0x20u /* not an error: the one-walk blended bounce ran out of
+                                           record space and redid part of the work with two walks */
 #define PRTGS_FLAG_ROUND_CAP 0x10u      /* a bounce ray needed more than PRTGS_BOUNCE_MAX_ROUNDS
                                            traversals; its walk stopped there */
 
@@ -95,6 +97,16 @@ typedef struct {
                                   hemisphere directions compacted), 2, 4, 8, 16, 32 or 64 */
     int32_t direction_parts;   /* waves that share one source group's directions, 1 .. 64; the
                                   blended bounce keeps at most PRTGS_BLEND_PARTS_MAX of them */
+    /* Blended bounce (bounces == 1, PRTGS_BOUNCE_BLEND) in one walk per ray
+     * instead of two: the walk that blends a ray's hits also yields its
+     * visibility, so no separate direct pass runs; the blended hits' weights
+     * (8 bytes each, about 38 per traced ray of a million-splat scene) wait in
+     * a record arena of this many 8-byte words in the workspace until every
+     * direct transfer exists.  Work whose records do not fit is redone by the
+     * two-walk method (PRTGS_FLAG_RECORDS_DEFERRED); the results agree with the
+     * two-walk method to the last bits of the visibility products.  0 = two
+     * walks (no arena). */
+    int64_t bounce_records;
 } prtgs_transfer_desc;
 
 #define PRTGS_BLEND_PARTS_MAX 8     /* blended bounce: direction parts with sums of their own */
@@ -186,7 +198,9 @@ prtgs_status prtgs_bvh_leaf_order(const void* bvh, int32_t n, int32_t* order /* 
 /* of per-ray cut depths and the per-lane hit lists of the persistent      */
 /* waves: min(n, 4096) waves and 768 MiB of lists + 512 MiB of hit records */
 /* + 1536 n bytes of per-part bounce sums (at K = 16) for the blend,        */
-/* min(n, 5120) waves and 960 MiB of lists in index mode.                   */
+/* min(n, 5120) waves and 960 MiB of lists in index mode.  With             */
+/* bounce_records > 0 also the record arena (8 bounce_records bytes) and 12 */
+/* bytes per work item (at most 8 n items).                                 */
 /* ---------------------------------------------------------------------- */
 size_t prtgs_transfer_workspace_bytes(const prtgs_transfer_desc* d /* host */, int32_t n);
 prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g /* host */, const void* bvh,
@@ -314,9 +328,12 @@ prtgs_status prtgs_glossy_view(int32_t n, int32_t K, const float* matrices, cons
  * (stats[0] its traced rays, [1]-[4] its traversal work over every round and
  * the depth intervals it walks), with stats[5] the hits blended (those with
  * transmittance >= T_eps in front: the contributing hits), stats[6] the hits
- * listed and stats[7] the traversal rounds, each summed over rays.  stats:
- * device array of 8 uint64, overwritten.  ws as for prtgs_precompute_transfer
- * with the same d.  Index mode: PRTGS_ERR_UNSUPPORTED. */
+ * listed and stats[7] the traversal rounds, each summed over rays; with
+ * bounce_records > 0 the one walk that replaces both is counted (stats[0] its
+ * traced rays, the rest as for the bounce walk).  stats: device array of 8
+ * uint64, overwritten.  ws as for prtgs_precompute_transfer with the same d,
+ * except that no record arena is needed (the size for bounce_records = 1).
+ * Index mode: PRTGS_ERR_UNSUPPORTED. */
 prtgs_status prtgs_traversal_stats(const prtgs_gaussians* g /* host */, const void* bvh,
                                    const prtgs_transfer_desc* d /* host */, int32_t first, int32_t count,
                                    uint64_t* stats, void* ws, size_t ws_bytes, hipStream_t stream);

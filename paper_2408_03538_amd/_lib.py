@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libprtgs.so")
 
 PRTGS_OK = 0
-ABI_VERSION = 4   # PRTGS_ABI_VERSION of include/prtgs.h that these declarations follow
+ABI_VERSION = 5   # PRTGS_ABI_VERSION of include/prtgs.h that these declarations follow
 STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "unsupported", 4: "HIP error"}
 ERR_WORKSPACE_TOO_SMALL = 2
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
@@ -17,6 +17,7 @@ FLAG_STACK_OVERFLOW = 0x2
 FLAG_BAD_TREE = 0x4
 FLAG_BAD_INDEX = 0x8
 FLAG_ROUND_CAP = 0x10
+FLAG_RECORDS_DEFERRED = 0x20   # informational: part of a one-walk blend was redone with two walks
 BOUNCE_HIT_LIST = 256     # PRTGS_BOUNCE_HIT_LIST
 BLEND_PARTS_MAX = 8       # PRTGS_BLEND_PARTS_MAX
 NOALLOC_SCRATCH_BYTES = 64 << 20   # PRTGS_NOALLOC_SCRATCH_MIB
@@ -40,7 +41,7 @@ class TransferDesc(ctypes.Structure):
     _fields_ = [("num_dirs", c_int32), ("sh_bands", c_int32), ("seed", c_uint64), ("bounces", c_int32),
                 ("sigma_cut", c_float), ("t_min", c_float), ("T_eps", c_float), ("alpha_min", c_float),
                 ("alpha_max", c_float), ("bounce_mode", c_int32), ("t_same", c_float),
-                ("sources_per_wave", c_int32), ("direction_parts", c_int32)]
+                ("sources_per_wave", c_int32), ("direction_parts", c_int32), ("bounce_records", ctypes.c_int64)]
 
 
 class Camera(ctypes.Structure):

@@ -95,6 +95,7 @@ class TransferParams:
     t_same: float = 1.0            # index mode: same-surface filter (1 = off)
     sources_per_wave: int = 0      # work split (0 = the library's choice); changes only the last bits
     direction_parts: int = 0
+    bounce_records: int = 0        # blend: record arena (8-byte words) for one walk per ray; 0 = two walks
 
     @property
     def K(self) -> int:
@@ -108,7 +109,7 @@ class TransferParams:
         mode = {"blend": _lib.BOUNCE_BLEND, "index": _lib.BOUNCE_INDEX}[self.bounce_mode]
         return _lib.TransferDesc(self.num_dirs, self.sh_bands, self.seed, self.bounces, self.sigma_cut, self.t_min,
                                  self.T_eps, self.alpha_min, self.alpha_max, mode, self.t_same,
-                                 self.sources_per_wave, self.direction_parts)
+                                 self.sources_per_wave, self.direction_parts, self.bounce_records)
 
     def cut(self) -> dict:
         return dict(sigma_cut=self.sigma_cut, t_min=self.t_min, T_eps=self.T_eps, alpha_min=self.alpha_min,
@@ -382,13 +383,16 @@ def splat_render(scene: Scene, colours: torch.Tensor, cam, max_instances: int | 
 def traversal_stats(scene: Scene, bvh: Bvh, params: TransferParams, first: int = 0, count: int | None = None,
                     workspace: Workspace | None = None) -> dict:
     """Single-ray work counts of the direct pass, or with ``params.bounces``
-    (blend) of the bounce walk (see prtgs_traversal_stats)."""
+    (blend) of the bounce walk, or of the one walk with ``bounce_records``
+    (see prtgs_traversal_stats)."""
     lib = _lib.load()
     n = scene.n
     count = n - first if count is None else count
     g = scene.c_struct()
     d = params.c_struct()
-    wbytes = lib.prtgs_transfer_workspace_bytes(ctypes.byref(d), n)
+    d_ws = params.c_struct()   # the counted walk keeps no records: no arena
+    d_ws.bounce_records = min(d_ws.bounce_records, 1)
+    wbytes = lib.prtgs_transfer_workspace_bytes(ctypes.byref(d_ws), n)
     ws = (workspace or Workspace()).get(wbytes, scene.device)
     stats = torch.zeros(8, dtype=torch.int64, device=scene.device)
     _lib.check(lib.prtgs_traversal_stats(ctypes.byref(g), _ptr(bvh.buffer), ctypes.byref(d), first, count, _ptr(stats),

@@ -79,13 +79,24 @@ prtgs_status check_desc(const prtgs_transfer_desc* d)
         return fail(PRTGS_ERR_INVALID_ARG, "sources_per_wave = %d not 0 or a power of two up to 64", g);
     if (d->direction_parts < 0 || d->direction_parts > 64)
         return fail(PRTGS_ERR_INVALID_ARG, "direction_parts = %d outside [0, 64]", d->direction_parts);
+    if (d->bounce_records < 0 || d->bounce_records > ((int64_t)1 << 40))
+        return fail(PRTGS_ERR_INVALID_ARG, "bounce_records = %lld outside [0, 2^40]", (long long)d->bounce_records);
     return PRTGS_OK;
+}
+
+// The blended bounce runs as one walk per ray when the caller gives it a record arena.
+bool one_walk(const prtgs_transfer_desc& d)
+{
+    return d.bounces == 1 && d.bounce_mode == PRTGS_BOUNCE_BLEND && d.bounce_records > 0;
 }
 
 struct TransferWs {
     size_t dirs, Y, dir_order, rayw, tdir, albedo, tcut, queue, hitkey, hitalpha, hitrec, partial, index, term0, term1,
-        total;
+        rec_top, item_head, item_deferred, rec, total;
+    int64_t items;   // one-walk blend: work items (direction part, source group)
 };
+
+int group_size(int count, int requested);
 
 TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
 {
@@ -124,6 +135,20 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     if (idx) off += align256(sizeof(float) * 3 * (size_t)K * (size_t)n);
     w.term1 = off;
     if (idx) off += align256(sizeof(float) * 3 * (size_t)K * (size_t)n);
+    // one-walk blend: the record arena and per work item its first block and deferral mark
+    const bool fused = one_walk(d);
+    const int G = group_size(n, d.sources_per_wave);
+    w.items = fused ? (int64_t)((n + G - 1) / G) * std::min(direction_parts(G, d.num_dirs, d.direction_parts),
+                                                               kBlendPartsMax)
+                    : 0;
+    w.rec_top = off;
+    if (fused) off += 256;
+    w.item_head = off;
+    off += align256(sizeof(int64_t) * (size_t)w.items);
+    w.item_deferred = off;
+    off += align256(sizeof(int32_t) * (size_t)w.items);
+    w.rec = off;
+    if (fused) off += align256(8 * (size_t)d.bounce_records);
     w.total = off;
     return w;
 }
@@ -265,6 +290,13 @@ TransferArgs transfer_args(const prtgs_gaussians* g, const void* bvh, const prtg
     a.G = group_size(count, d->sources_per_wave);
     a.Q_req = d->direction_parts;
     a.flags = reinterpret_cast<unsigned*>(w);
+    if (one_walk(*d)) {
+        a.rec = reinterpret_cast<uint64_t*>(w + W.rec);
+        a.rec_words = (uint64_t)d->bounce_records;
+        a.rec_top = reinterpret_cast<unsigned long long*>(w + W.rec_top);
+        a.item_head = reinterpret_cast<int64_t*>(w + W.item_head);
+        a.item_deferred = reinterpret_cast<int32_t*>(w + W.item_deferred);
+    }
     return a;
 }
 
@@ -308,6 +340,7 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g, const void* bvh
     if (e != hipSuccess) return hip_status(e, "direction table");
     if (count == 0) return ok();
     TransferArgs a = transfer_args(g, bvh, d, first, count, transfer, vis, w, W);
+    if (one_walk(*d)) return hip_status(launch_transfer_fused(a, stream), "one-walk blended bounce");
     e = launch_transfer_direct(a, stream);
     if (e != hipSuccess) return hip_status(e, "direct transfer");
     if (d->bounces > 0 && d->bounce_mode == PRTGS_BOUNCE_BLEND) {
@@ -583,6 +616,10 @@ prtgs_status prtgs_traversal_stats(const prtgs_gaussians* g, const void* bvh, co
         return fail(PRTGS_ERR_INVALID_ARG, "source range [%d, %d + %d) outside [0, %d)", first, first, count, n);
     if (bounce && (first != 0 || count != n))
         return fail(PRTGS_ERR_INVALID_ARG, "a bounce needs every source's direct transfer: use first = 0, count = n");
+    // the counted one-walk blend writes no records: a one-word arena is enough
+    prtgs_transfer_desc d1 = *d;
+    if (one_walk(d1)) d1.bounce_records = 1;
+    d = &d1;
     TransferWs W = transfer_ws_layout(*d, n);
     if (ws_bytes < W.total)
         return fail(PRTGS_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, needs %zu", ws_bytes, W.total);
@@ -594,6 +631,7 @@ prtgs_status prtgs_traversal_stats(const prtgs_gaussians* g, const void* bvh, co
     TransferArgs a = transfer_args(g, bvh, d, first, count, nullptr, nullptr, w, W);
     unsigned long long* st64 = reinterpret_cast<unsigned long long*>(stats);
     if (!bounce) return hip_status(launch_transfer_direct(a, stream, st64), "traversal stats");
+    if (one_walk(*d)) return hip_status(launch_fused_stats(a, stream, st64), "traversal stats");
     // the direct pass (its transfers and cut depths feed the walk), then the counted walk
     e = launch_transfer_direct(a, stream);
     if (e == hipSuccess) e = launch_bounce_stats(a, stream, st64);

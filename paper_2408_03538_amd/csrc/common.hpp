@@ -167,9 +167,23 @@ struct TransferArgs {
                             // contiguous share of the direction batches (part-major)
     int Q_req;              // the caller's direction parts (0 = the default)
     unsigned* flags;
+    // blend in one walk per ray (transfer.hip, fused walk): each work item's
+    // records (leaf rank, weight) in a chain of blocks of the arena
+    uint64_t* rec;                 // arena of rec_words 8-byte words
+    uint64_t rec_words;
+    unsigned long long* rec_top;   // words taken so far (may pass rec_words)
+    int64_t* item_head;            // [items] first block of each item, -1: none
+    int32_t* item_deferred;        // [items] 1: its records did not fit, the two-walk pass redoes it
 };
+// A record block: word 0 the next block of the item (~0: none), words 1-16
+// the 64 lanes' record counts (16 bits each), then the records, lane by lane.
+constexpr int kRecHeaderWords = 17;
 hipError_t launch_transfer_direct(const TransferArgs& a, hipStream_t stream, unsigned long long* stats = nullptr);
 hipError_t launch_transfer_bounce(const TransferArgs& a, hipStream_t stream);
+// the blended bounce in one walk per ray: visibility, projection and bounce (needs the arena)
+hipError_t launch_transfer_fused(const TransferArgs& a, hipStream_t stream);
+// the one walk with its work tallied into stats[8] (visibility and records not kept)
+hipError_t launch_fused_stats(const TransferArgs& a, hipStream_t stream, unsigned long long* stats);
 hipError_t launch_transfer_index(const TransferArgs& a, hipStream_t stream);
 // the blended bounce's walk with its work tallied into stats[8] (no transfer written)
 hipError_t launch_bounce_stats(const TransferArgs& a, hipStream_t stream, unsigned long long* stats);

@@ -385,6 +385,108 @@ __device__ inline void merge_chunk(uint64_t (&kk)[N], float (&aa)[N], uint64_t (
             if ((i & dist) == 0) cas_pair(bk[i], ba[i], bk[i + dist], ba[i + dist]);
 }
 
+// Sums a lane's blended-hit records (leaf rank, weight), in blend order, into
+// its source's 3 K bounce sums of direction part `part` (Eq. 20-22, 30-33:
+// rho_j,c w t_dir[j] per record), the D lanes of a source summed first.  One
+// wave owns a (part, source) pair, so the read-modify-write needs no atomics.
+template <int K>
+__device__ inline void sum_records(const TransferArgs& a, const int2* rec, int cnt, int D, bool valid, int part,
+                                   int orig, float scale)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    float acc[3][K];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[ch][k] = 0.0f;
+    for (int q = 0; q < cnt; ++q) {
+        const int2 e = rec[q];
+        const int r = e.x;
+        const float w = __int_as_float(e.y);
+        const float4 rho = a.albedo_sorted[r];
+        float tv[K];
+        if constexpr (K % 4 == 0) {
+            const float4* td = reinterpret_cast<const float4*>(a.tdir_sorted + (size_t)r * K);
+#pragma unroll
+            for (int k4 = 0; k4 < K / 4; ++k4) {
+                const float4 v = td[k4];
+                tv[4 * k4] = v.x;
+                tv[4 * k4 + 1] = v.y;
+                tv[4 * k4 + 2] = v.z;
+                tv[4 * k4 + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) tv[k] = a.tdir_sorted[(size_t)r * K + k];
+        }
+        const float r0 = rho.x * w, r1 = rho.y * w, r2 = rho.z * w;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            acc[0][k] = fmaf(r0, tv[k], acc[0][k]);
+            acc[1][k] = fmaf(r1, tv[k], acc[1][k]);
+            acc[2][k] = fmaf(r2, tv[k], acc[2][k]);
+        }
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float* out = a.partial + (((size_t)part * a.n + orig) * 3 + ch) * K;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float v = segment_sum(acc[ch][k], D) * scale;
+            if (valid && (lane % D) == 0) out[k] += v;
+        }
+    }
+}
+
+// Exclusive prefix sum of v over the lanes of the wave.
+__device__ inline int lane_prefix(int v)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    int incl = v;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int up = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += up;
+    }
+    return incl - v;
+}
+
+// One-walk blend: the round's records (each lane's cnt of them) go to a new
+// block at the end of the item's chain, to be summed once every direct
+// transfer exists (accumulate_kernel).  An item whose block does not fit in
+// the arena is marked deferred: its later rounds write nothing, the
+// accumulation skips it and the two-walk pass redoes it.
+__device__ inline void emit_records(const TransferArgs& a, const int2* lrec, int cnt, int item, int64_t& prev_block,
+                                    bool& item_def)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    int tot = cnt;
+    for (int off = kWave / 2; off >= 1; off >>= 1) tot += __shfl_xor(tot, off, kWave);
+    if (tot == 0 || item_def) return;   // uniform
+    const unsigned long long need = (unsigned long long)kRecHeaderWords + (unsigned long long)tot;
+    unsigned long long at = 0;
+    if (lane == 0) at = atomicAdd(a.rec_top, need);
+    at = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(at >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)at);
+    if (at + need > a.rec_words) {
+        item_def = true;
+        if (lane == 0) {
+            a.item_deferred[item] = 1;
+            raise_flag(a.flags, PRTGS_FLAG_RECORDS_DEFERRED);
+        }
+        return;
+    }
+    uint64_t* blk = a.rec + at;
+    if (lane == 0) {
+        blk[0] = ~0ull;   // the end of the chain until a next block links in
+        if (prev_block < 0) a.item_head[item] = (int64_t)at;
+        else a.rec[prev_block] = at;
+    }
+    reinterpret_cast<uint16_t*>(blk + 1)[lane] = (uint16_t)cnt;
+    int2* dst = reinterpret_cast<int2*>(blk + kRecHeaderWords) + lane_prefix(cnt);
+    for (int q = 0; q < cnt; ++q) dst[q] = lrec[q];
+    prev_block = (int64_t)at;
+}
+
 // kIndex: the paper's own bounce instead of the blend -- the same walk, but
 // each ray records the hit of largest alpha_j T_j max(-w . n_j, 0) among the
 // hits with T_j <= t_same (the nearer one on equal weights) in the index
@@ -392,7 +494,17 @@ __device__ inline void merge_chunk(uint64_t (&kk)[N], float (&aa)[N], uint64_t (
 // entries are loaded together in the selection.
 // kCount (blend only): the walk also tallies its work into stats (see
 // launch_bounce_stats); the results are the same.
-template <int K, bool kIndex, int kScan, bool kCount = false>
+// kFused (blend only): one walk per ray for both passes.  No cut comes from a
+// direct pass: until the running product of the hits found falls below
+// T_eps (in traversal order, as the direct pass multiplies them) the walk
+// lists every hit; from then on the farthest of those hits is the cut, the
+// checkpoints split [t_lo, cut] (the last one holding that product, the
+// others T, a bound that the hits found later tighten), and the walk goes on
+// as the two-walk blend does.  At the end of its rounds the ray's blend gives
+// its visibility (the product over all its hits, 0 once below T_eps), written
+// where the direct pass writes it, with the deepest cut found; the blended
+// hits' records go to the arena (emit_records) instead of being summed.
+template <int K, bool kIndex, int kScan, bool kCount = false, bool kFused = false>
 __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long long* stats = nullptr)
 {
     constexpr int M = kHitList;
@@ -420,7 +532,11 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
         if (lane == 0) item = (int)atomicAdd(a.queue, 1u);
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= groups * a.Q) break;   // uniform: every wave leaves once the counter passes the last item
+        // (two-walk pass after a one-walk blend) only the items whose records did not fit
+        if (!kFused && a.item_deferred && a.item_deferred[item] == 0) continue;
         const int part = item / groups, grp = item % groups;
+        int64_t prev_block = -1;   // (kFused) the item's last record block
+        bool item_def = false;     // (kFused) the item's records did not fit
 
         const int local = grp * G + lane / D;
         const bool valid = local < a.count;
@@ -441,6 +557,11 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
             const float c = nrm.x * d.wx + nrm.y * d.wy + nrm.z * d.wz;
             bool pending = valid && inrange && c > 0.0f;
             if (kIndex && valid && inrange && !pending) a.index[(size_t)orig * a.S + s] = -1;
+            if (kFused && !kCount && valid && inrange && !pending) {   // below the horizon, as the direct pass writes it
+                a.rayw[(size_t)pos * a.count + local] = 0.0f;
+                if (a.vis) a.vis[(size_t)orig * a.S + s] = -1.0f;
+                a.tcut[(size_t)local * a.S + pos] = 0.0f;
+            }
             if (__ballot(pending) == 0ull) continue;
             const bool traced = pending;
             if (kCount && traced) ++n_traced;
@@ -448,7 +569,9 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
             const float wc = c * kInvPi;
             // No hit beyond tc can carry weight: the direct pass saw the
             // transmittance fall below T_eps using hits no farther than tc.
-            const float tc = pending ? a.tcut[(size_t)local * a.S + pos] : 0.0f;
+            // (kFused: no cut yet; tck is the deepest the walk has found.)
+            const float tc = kFused ? INFINITY : (pending ? a.tcut[(size_t)local * a.S + pos] : 0.0f);
+            float tck = tc;
             float T = 1.0f;
             float bestW = 0.0f;   // (kIndex) largest weight so far and its leaf rank
             int bestr = -1;
@@ -460,27 +583,27 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                 // Every round blends at least one listed hit (compact keeps the
                 // nearest), so a ray ends within as many rounds as it has hits;
                 // the cap bounds the work of a pathological scene.
-                if (pending && (__atomic_load_n(a.flags, __ATOMIC_RELAXED) & PRTGS_FLAG_BAD_TREE)) {
-                    pending = false;
-                    continue;
-                }
+                // (No early exit for the lanes that stop: the record emission
+                // needs every lane of the wave active; a stopped lane traces,
+                // lists and blends nothing.)
+                if (pending && (__atomic_load_n(a.flags, __ATOMIC_RELAXED) & PRTGS_FLAG_BAD_TREE)) pending = false;
                 if (pending && ++rounds > kMaxRounds) {
                     raise_flag(a.flags, PRTGS_FLAG_ROUND_CAP);
                     pending = false;
-                    continue;
                 }
                 if (kCount && pending) ++n_rounds;
                 int cnt = 0;
                 float sum_t = 0.0f;         // of the listed hits (compaction pivot)
                 uint64_t k_over = kNoHit;   // hits from here on wait for the next round
                 bool live = pending;
-                float tlo = started ? fmaxf(hp.t_min, key_t(k_last)) : hp.t_min, thi = tc;
+                float tlo = started ? fmaxf(hp.t_min, key_t(k_last)) : hp.t_min, thi = tck;
+                float Tr = T, tfar = 0.0f;   // (kFused, no cut yet) product and depth of the hits found
                 // Checkpoints tlo + (b + 1) tstep split [tlo, tc]: P[b] is T times
                 // the (1 - alpha) of the hits found so far in front of checkpoint
                 // b.  The hits in front of it are a subset of all of them, so
                 // once P[b] < T_eps the walk ends there and nothing beyond the
                 // checkpoint is needed.
-                const float tstep = tc < INFINITY ? (tc - tlo) * (1.0f / (float)kCheck) : 0.0f;
+                float tstep = tck < INFINITY ? (tck - tlo) * (1.0f / (float)kCheck) : 0.0f;
                 float P[kCheck];
 #pragma unroll
                 for (int b = 0; b < kCheck; ++b) P[b] = T;
@@ -538,14 +661,27 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                     const bool ins = hit & (h.t <= thi) & (!started | (key > k_last)) & (key < k_over);
                     if (ins) {
                         if (tstep > 0.0f) {
-                            float cut = thi;
+                            float cut = INFINITY;
 #pragma unroll
                             for (int b = 0; b < kCheck; ++b) {
                                 const float tb = tlo + tstep * (float)(b + 1);
                                 P[b] = h.t <= tb ? P[b] * (1.0f - h.alpha) : P[b];
                                 cut = P[b] < hp.T_eps ? fminf(cut, tb) : cut;
                             }
-                            thi = cut;
+                            thi = fminf(thi, cut);
+                            if (kFused) tck = fminf(tck, cut);
+                        } else if (kFused) {
+                            Tr *= 1.0f - h.alpha;
+                            tfar = fmaxf(tfar, h.t);
+                            if (Tr < hp.T_eps) {
+                                // every hit found so far lies in front of tfar: the cut
+                                tck = tfar;
+                                thi = fminf(thi, tfar);
+                                tstep = (tck - tlo) * (1.0f / (float)kCheck);
+#pragma unroll
+                                for (int b = 0; b < kCheck - 1; ++b) P[b] = T;
+                                P[kCheck - 1] = Tr;
+                            }
                         }
                         if (cnt == M) compact();
                         if (key < k_over) {
@@ -645,50 +781,20 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                 // the source's transfer (the D lanes of a source summed
                 // first).  The sums live only here, not across the selection
                 // or the traversal, which keeps both free of spills.
-                if constexpr (!kIndex) {
-                    float acc[3][K];
-#pragma unroll
-                    for (int ch = 0; ch < 3; ++ch)
-#pragma unroll
-                        for (int k = 0; k < K; ++k) acc[ch][k] = 0.0f;
-                    for (int q = 0; q < nrec; ++q) {
-                        const int2 e = lrec[q];
-                        const int r = e.x;
-                        const float w = __int_as_float(e.y);
-                        const float4 rho = a.albedo_sorted[r];
-                        float tv[K];
-                        if constexpr (K % 4 == 0) {
-                            const float4* td = reinterpret_cast<const float4*>(a.tdir_sorted + (size_t)r * K);
-#pragma unroll
-                            for (int k4 = 0; k4 < K / 4; ++k4) {
-                                const float4 v = td[k4];
-                                tv[4 * k4] = v.x;
-                                tv[4 * k4 + 1] = v.y;
-                                tv[4 * k4 + 2] = v.z;
-                                tv[4 * k4 + 3] = v.w;
-                            }
-                        } else {
-#pragma unroll
-                            for (int k = 0; k < K; ++k) tv[k] = a.tdir_sorted[(size_t)r * K + k];
-                        }
-                        const float r0 = rho.x * w, r1 = rho.y * w, r2 = rho.z * w;
-#pragma unroll
-                        for (int k = 0; k < K; ++k) {
-                            acc[0][k] = fmaf(r0, tv[k], acc[0][k]);
-                            acc[1][k] = fmaf(r1, tv[k], acc[1][k]);
-                            acc[2][k] = fmaf(r2, tv[k], acc[2][k]);
-                        }
-                    }
-#pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) {
-                        // this part's own sums (one wave owns a (part, source) pair)
-                        float* out = a.partial + (((size_t)part * a.n + orig) * 3 + ch) * K;
-#pragma unroll
-                        for (int k = 0; k < K; ++k) {
-                            const float v = segment_sum(acc[ch][k], D) * scale;
-                            if (valid && (lane % D) == 0) out[k] += v;
-                        }
-                    }
+                if constexpr (kFused) {
+                    if constexpr (!kCount) emit_records(a, lrec, nrec, item, prev_block, item_def);
+                } else if constexpr (!kIndex) {
+                    sum_records<K>(a, lrec, nrec, D, valid, part, orig, scale);
+                }
+            }
+            if (kFused && traced) {
+                // the ray's visibility (Eq. 4's product over every hit, 0 once below
+                // T_eps), as the direct pass writes it, and the deepest cut found
+                const float V = T < hp.T_eps ? 0.0f : T;
+                if constexpr (!kCount) {
+                    a.rayw[(size_t)pos * a.count + local] = V * c;
+                    if (a.vis) a.vis[(size_t)orig * a.S + s] = V;
+                    a.tcut[(size_t)local * a.S + pos] = tck;
                 }
             }
             if (kIndex && traced) a.index[(size_t)orig * a.S + s] = bestr >= 0 ? a.order[bestr] : -1;
@@ -732,6 +838,50 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceW
     TransferArgs a, unsigned long long* stats)
 {
     bounce_walk<K, false, 4, true>(a, stats);
+}
+// the blend in one walk per ray, and the same with its work tallied
+template <int K>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceWavesPerSimd))) void fused_kernel(
+    TransferArgs a)
+{
+    bounce_walk<K, false, 4, false, true>(a);
+}
+template <int K>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceWavesPerSimd))) void fused_count_kernel(
+    TransferArgs a, unsigned long long* stats)
+{
+    bounce_walk<K, false, 4, true, true>(a, stats);
+}
+
+// The one-walk blend's records summed once every direct transfer exists: one
+// wave per work item, its blocks in the order the walk wrote them, each
+// lane's records in blend order (sum_records, the arithmetic of the two-walk
+// blend).  Deferred items are left to the two-walk pass.
+template <int K>
+__global__ __launch_bounds__(kBlock) void accumulate_kernel(TransferArgs a)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int G = a.G, D = kWave / G;
+    const int groups = (a.count + G - 1) / G;
+    const int items = groups * a.Q;
+    const float scale = kFourPi / (float)a.S;
+    for (int item = (int)((blockIdx.x * kBlock + threadIdx.x) / kWave); item < items;
+         item += (int)(gridDim.x * (kBlock / kWave))) {
+        if (a.item_deferred[item]) continue;
+        int64_t at = a.item_head[item];
+        const int part = item / groups, grp = item % groups;
+        const int local = grp * G + lane / D;
+        const bool valid = local < a.count;
+        const int orig = valid ? a.order[a.first + local] : 0;
+        while (at >= 0) {
+            const uint64_t* blk = a.rec + at;
+            const int cnt = reinterpret_cast<const uint16_t*>(blk + 1)[lane];
+            const int2* rec = reinterpret_cast<const int2*>(blk + kRecHeaderWords) + lane_prefix(cnt);
+            sum_records<K>(a, rec, cnt, D, valid, part, orig, scale);
+            const uint64_t nx = blk[0];
+            at = nx == ~0ull ? -1 : (int64_t)nx;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -863,7 +1013,71 @@ hipError_t launch_bounce_k(const TransferArgs& a, hipStream_t stream, unsigned l
     return hipGetLastError();
 }
 
+// The blend in one walk per ray: the walk (visibility, cut depths, records),
+// the projection (the direct transfers the records need), the records' sums,
+// the two-walk pass over the items whose records did not fit (a launch whose
+// waves skip every other item), and the parts added in order.
+template <int K>
+hipError_t launch_fused_k(const TransferArgs& a, hipStream_t stream, unsigned long long* stats)
+{
+    TransferArgs b = a;
+    b.Q = std::min(direction_parts(a.G, a.S, a.Q_req), kBlendPartsMax);
+    const int64_t items = (int64_t)((a.count + a.G - 1) / a.G) * b.Q;
+    hipError_t e = fill_u32(a.queue, 0u, 1, stream);
+    if (e == hipSuccess) e = fill_u32(reinterpret_cast<uint32_t*>(a.rec_top), 0u, 2, stream);
+    if (e == hipSuccess) e = fill_u32(reinterpret_cast<uint32_t*>(a.item_head), 0xffffffffu, 2 * (size_t)items, stream);
+    if (e == hipSuccess) e = fill_u32(reinterpret_cast<uint32_t*>(a.item_deferred), 0u, (size_t)items, stream);
+    if (e == hipSuccess && !stats)
+        e = fill_u32(reinterpret_cast<uint32_t*>(b.partial), 0u, (size_t)b.Q * a.n * 3 * a.K, stream);
+    if (e != hipSuccess) return e;
+    const int cap = bounce_waves(a.n, false);
+    const int waves = items < cap ? (int)items : cap;
+    const dim3 grid((waves + kBlock / kWave - 1) / (kBlock / kWave));
+    if (stats) {
+        hipLaunchKernelGGL(fused_count_kernel<K>, grid, dim3(kBlock), 0, stream, b, stats);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(fused_kernel<K>, grid, dim3(kBlock), 0, stream, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(project_kernel<K>, dim3((a.count + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t acc_blocks = std::min<int64_t>((items + kBlock / kWave - 1) / (kBlock / kWave), 65536);
+    hipLaunchKernelGGL(accumulate_kernel<K>, dim3((unsigned)acc_blocks), dim3(kBlock), 0, stream, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = fill_u32(a.queue, 0u, 1, stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(bounce_kernel<K>, grid, dim3(kBlock), 0, stream, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t count = (size_t)a.n * 3 * a.K;
+    hipLaunchKernelGGL(add_parts_kernel, dim3((unsigned)std::min<size_t>((count + 255) / 256, 65536)), dim3(256), 0,
+                       stream, a.transfer, b.partial, count, b.Q);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_transfer_fused(const TransferArgs& a, hipStream_t stream)
+{
+    if (a.count <= 0) return hipSuccess;
+    switch (a.K) {
+        case 1: return launch_fused_k<1>(a, stream, nullptr);
+        case 4: return launch_fused_k<4>(a, stream, nullptr);
+        case 9: return launch_fused_k<9>(a, stream, nullptr);
+        case 16: return launch_fused_k<16>(a, stream, nullptr);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fused_stats(const TransferArgs& a, hipStream_t stream, unsigned long long* stats)
+{
+    if (a.count <= 0) return hipSuccess;
+    switch (a.K) {
+        case 1: return launch_fused_k<1>(a, stream, stats);
+        case 4: return launch_fused_k<4>(a, stream, stats);
+        case 9: return launch_fused_k<9>(a, stream, stats);
+        case 16: return launch_fused_k<16>(a, stream, stats);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_transfer_direct(const TransferArgs& a, hipStream_t stream, unsigned long long* stats)
 {

@@ -37,7 +37,7 @@ def test_binding_covers_the_header():
 
 
 def test_abi_version(lib):
-    assert lib.prtgs_abi_version() == 4
+    assert lib.prtgs_abi_version() == 5
 
 
 def test_size_queries(lib):
@@ -260,3 +260,25 @@ def test_noalloc_host_validation(lib):
                                                  None) == 3
     assert lib.prtgs_precompute_transfer_noalloc(ctypes.byref(g), 257, ctypes.byref(d), 0, 10, 256, None, None,
                                                  None) == 1     # misaligned BVH
+
+
+def test_one_walk_workspace(lib):
+    """bounce_records (blend, one bounce) adds the record arena (8 bytes a
+    word), a 256-byte counter and, per work item (direction part x source
+    group), an 8-byte chain head and a 4-byte deferral mark; it is ignored in
+    index mode and without a bounce, and a negative size is refused."""
+    from paper_2408_03538_amd import _lib
+    n, R = 20000, 1_000_000
+    args = (64, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0, 16, 4)
+    size = lambda *a: lib.prtgs_transfer_workspace_bytes(ctypes.byref(_lib.TransferDesc(*a)), n)
+    two, one = size(*args, 0), size(*args, R)
+    items = (n + 15) // 16 * 4
+    assert one - two == 256 + align(8 * items) + align(4 * items) + align(8 * R)
+    index = (64, 3, 0, 3, 3.0, 0.0, 1e-4, 0.0, 0.99, 1, 1.0, 16, 4)
+    assert size(*index, R) == size(*index, 0)
+    direct = (64, 3, 0, 0, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0, 16, 4)
+    assert size(*direct, R) == size(*direct, 0)
+    assert size(*args, -1) == 0
+    # the binding passes the field through
+    import paper_2408_03538_amd as prt
+    assert prt.TransferParams(num_dirs=64, sh_bands=3, bounces=1, bounce_records=R).c_struct().bounce_records == R
