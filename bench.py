@@ -56,8 +56,8 @@ FLOPS_PER_PRIM_TEST = 70
 MEASURED = {
     "direct_surface100k": {"sources_sha256_16": "014a201dfedefb11", "bytes_per_launch": 7.270e9,
                            "valu_instructions_per_launch": 1.1732e10},
-    "bounce_million": {"sources_sha256_16": "014a201dfedefb11", "bytes_per_launch": 3.321e12,
-                       "valu_instructions_per_launch": 1.3217e12},
+    "one_walk_million": {"sources_sha256_16": "unmeasured", "bytes_per_launch": None,
+                         "valu_instructions_per_launch": None},
 }
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
                   "paper_2408_03538_amd/csrc/common.hpp", "paper_2408_03538_amd/csrc/capi.hip"]   # capi: work split
@@ -180,6 +180,7 @@ def main():
     log("generating the million-splat workload")
     arr, sc, params, light = workload_setup(prt, torch, scenegen, "million")
     n, S = sc.n, params.num_dirs
+    one_walk_stats = None
     if args.index_only:
         bvh = prt.build_bvh(sc)
         p_idx = prt.TransferParams(num_dirs=S, sh_bands=params.sh_bands, bounce_mode="index", bounces=1)
@@ -193,6 +194,9 @@ def main():
             log(f"index matrix (direct pass + index walk): {a.elapsed_time(b):.1f} ms")
             del idx
         return
+    # the blend in one walk per ray: its records' arena sized from a counted walk
+    one_walk_stats, params.bounce_records = record_arena(prt, torch, sc, params)
+    log(f"record arena: {params.bounce_records / 1e9:.2f}e9 words ({8 * params.bounce_records / 1e9:.1f} GB)")
     res = time_steps(prt, torch, np, sc, params, light, args.steps, args.warmup)
     ms_step = res["ms_step"]
     log(f"step {ms_step:.1f} ms: build {res['build']:.2f} ms, transfer {res['transfer']:.1f} ms, "
@@ -214,11 +218,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "million: unit sphere on a 4x4 plane (200,000 splats) + 20 ellipsoid shells x 40,000 "
-                               "splats, N=1,000,000, S=512, 16 SH coeffs x RGB, direct + 1 bounce",
+                               "splats, N=1,000,000, S=512, 16 SH coeffs x RGB, direct + 1 bounce (one walk per ray)",
                    "n_splats": n, "num_dirs": S, "sh_coeffs": params.K, "channels": params.channels,
                    "bounces": params.bounces},
     }
-    result.update(million_breakdown(prt, torch, np, sc, params, res, args.steps))
+    result.update(million_breakdown(prt, torch, np, sc, params, res, args.steps, one_walk_stats))
     result["relit_splats_per_s"] = round(n / (res["relight"] * 1e-3), 1)
     transfer_out, bvh = res["transfer_out"], res["bvh"]
     res.clear()
@@ -270,30 +274,49 @@ def roofline_of(kernel, stats, ms, bytes_per_unit, extra_unit_bytes=None, counte
     return out
 
 
-def million_breakdown(prt, torch, np, sc, params, res, steps):
-    """Per-pass times of the headline step (HIP events on the library's
-    stream), the single-ray work of each pass, and the roofline of the bounce
-    walk, the dominant kernel."""
-    direct = prt.TransferParams(num_dirs=params.num_dirs, sh_bands=params.sh_bands, bounces=0)
-    out = torch.zeros((sc.n, 1, params.K), dtype=torch.float32, device="cuda")
-    ws = prt.Workspace()
-    prt.precompute_transfer(sc, res["bvh"], direct, out=out, workspace=ws)
-    times = []
-    for _ in range(max(3, min(steps, 5))):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        prt.precompute_transfer(sc, res["bvh"], direct, out=out, workspace=ws)
-        b.record()
-        torch.cuda.synchronize()
-        times.append(a.elapsed_time(b))
-    t_direct = float(np.median(times))
-    t_transfer = float(np.median(res["transfer_all"]))
-    t_bounce = t_transfer - t_direct
-    del out
-    sd = prt.traversal_stats(sc, res["bvh"], direct, workspace=ws)
-    del ws
+def record_arena(prt, torch, sc, params):
+    """Work counts of the one walk (a counted run, outside any timed region)
+    and the record arena they call for: one 8-byte record per blended hit,
+    plus a 17-word block header per (work item, direction batch, round), with
+    5% to spare; what does not fit would be redone by two walks."""
+    bvh = prt.build_bvh(sc)
+    probe = prt.TransferParams(**{**params.__dict__, "bounce_records": 1})
+    st = prt.traversal_stats(sc, bvh, probe)
+    del bvh
     torch.cuda.empty_cache()
-    sb = prt.traversal_stats(sc, res["bvh"], params)
+    blocks = sc.n * params.num_dirs // 64 * st["rounds"] / max(1, st["traced_rays"])
+    return st, int(1.05 * (st["blended_hits"] + 17 * blocks)) + (1 << 20)
+
+
+def million_breakdown(prt, torch, np, sc, params, res, steps, sb):
+    """The headline transfer call (the blend in one walk per ray) beside the
+    direct pass alone and the two-walk blend (HIP events on the library's
+    stream), the single-ray work of each walk, and the roofline of the
+    one-walk call, which is the step's dominant work."""
+    def timed(p, channels):
+        out = torch.zeros((sc.n, channels, p.K), dtype=torch.float32, device="cuda")
+        ws = prt.Workspace()
+        prt.precompute_transfer(sc, res["bvh"], p, out=out, workspace=ws)
+        times = []
+        for _ in range(max(3, min(steps, 5))):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            prt.precompute_transfer(sc, res["bvh"], p, out=out, workspace=ws)
+            b.record()
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+        prt.check_flags(ws.buf, "transfer")
+        del out, ws
+        torch.cuda.empty_cache()
+        return float(np.median(times))
+
+    direct = prt.TransferParams(num_dirs=params.num_dirs, sh_bands=params.sh_bands, bounces=0)
+    two = prt.TransferParams(**{**params.__dict__, "bounce_records": 0})
+    t_direct = timed(direct, 1)
+    t_two = timed(two, 3)
+    t_transfer = float(np.median(res["transfer_all"]))
+    sd = prt.traversal_stats(sc, res["bvh"], direct)
+    s2 = prt.traversal_stats(sc, res["bvh"], two)
     torch.cuda.empty_cache()
     K = params.K
     td = sd["traced_rays"]
@@ -304,33 +327,42 @@ def million_breakdown(prt, torch, np, sc, params, res, steps):
     hit_bytes = 4 * K + 12
     # direct: traversal + the ray's weight written and read back by the projection
     b_direct = BYTES_PER_BOX_TEST * d_box + BYTES_PER_PRIM_TEST * d_prim
-    # bounce: its own (culled) traversal, the hits blended, the cut depth read
-    b_bounce = BYTES_PER_BOX_TEST * b_box + BYTES_PER_PRIM_TEST * b_prim + hit_bytes * blended + 4
-    log(f"million: direct {t_direct:.0f} ms ({d_box:.0f} box / {d_prim:.0f} Gaussian tests per ray), bounce "
-        f"{t_bounce:.0f} ms ({b_box:.0f} / {b_prim:.0f} per ray, {blended:.1f} blended / {listed:.1f} listed hits, "
-        f"{rounds:.3f} rounds)")
-    roof = roofline_of("bounce_kernel<16> (the blended bounce walk: culled traversal, nearest-first selection, blend; "
-                       "timed as the bounce call minus the direct call)",
-                       sb, t_bounce, b_bounce,
+    # one walk: its traversal, the hits blended (their direct transfer and
+    # albedo read), the ray's weight written for and read by the projection
+    b_one = BYTES_PER_BOX_TEST * b_box + BYTES_PER_PRIM_TEST * b_prim + hit_bytes * blended + 8
+    log(f"million: one-walk call {t_transfer:.0f} ms ({b_box:.0f} box / {b_prim:.0f} Gaussian tests per ray, "
+        f"{blended:.1f} blended / {listed:.1f} listed hits, {rounds:.3f} rounds); two walks {t_two:.0f} ms, "
+        f"direct pass alone {t_direct:.0f} ms ({d_box:.0f} / {d_prim:.0f} per ray)")
+    roof = roofline_of("fused_kernel<16> + project_kernel + accumulate_kernel: the whole one-walk transfer call "
+                       "(visibility, projection, bounce; the walk is ~96% of it), timed around the call",
+                       sb, t_transfer, b_one,
                        {"box_tests": round(b_box, 2), "prim_tests": round(b_prim, 2),
                         "blended_hits": round(blended, 2), "bytes_per_blended_hit": hit_bytes,
-                        "listed_hits": round(listed, 2), "rounds": round(rounds, 4), "cut_depth_bytes": 4},
-                       measured("bounce_million"))
-    direct_roof = roofline_of("direct_kernel + project_kernel (visibility traversal, then SH projection)", sd,
+                        "listed_hits": round(listed, 2), "rounds": round(rounds, 4), "ray_weight_bytes": 8},
+                       measured("one_walk_million"))
+    roof["packet_node_visits_per_64_rays"] = round(sb["wave_node_visits"] / (tb / 64), 1)
+    roof["packet_gaussian_visits_per_64_rays"] = round(sb["wave_prim_visits"] / (tb / 64), 1)
+    direct_roof = roofline_of("direct_kernel + project_kernel (visibility traversal, then SH projection; "
+                              "the direct transfer alone, not part of the step)", sd,
                               t_direct, b_direct, {"box_tests": round(d_box, 2), "prim_tests": round(d_prim, 2)})
     direct_roof["packet_node_visits_per_64_rays"] = round(sd["wave_node_visits"] / (td / 64), 1)
     direct_roof["packet_gaussian_visits_per_64_rays"] = round(sd["wave_prim_visits"] / (td / 64), 1)
-    roof["packet_node_visits_per_64_rays"] = round(sb["wave_node_visits"] / (tb / 64), 1)
-    roof["packet_gaussian_visits_per_64_rays"] = round(sb["wave_prim_visits"] / (tb / 64), 1)
+    t2 = s2["traced_rays"]
     return {
-        "breakdown_ms": {"build_bvh": round(res["build"], 3), "direct_pass": round(t_direct, 2),
-                         "bounce_pass": round(t_bounce, 2), "relight": round(res["relight"], 4),
-                         "transfer_call": round(t_transfer, 2)},
+        "breakdown_ms": {"build_bvh": round(res["build"], 3), "transfer_call": round(t_transfer, 2),
+                         "relight": round(res["relight"], 4)},
         "traced_rays": td,
-        "direct_traced_grays_per_s": round(td / (t_direct * 1e-3) / 1e9, 4),
+        "record_arena_words": params.bounce_records,
         "grays_per_s_without_build": round(sc.n * params.num_dirs / ((res["ms_step"] - res["build"]) * 1e-3) / 1e9,
                                            5),
         "roofline": roof,
+        "two_walks": {"what": "the same transfer with the direct pass and the bounce walk as two walks "
+                              "(bounce_records = 0), not part of the step",
+                      "transfer_call_ms": round(t_two, 2), "direct_pass_ms": round(t_direct, 2),
+                      "bounce_walk_ms": round(t_two - t_direct, 2),
+                      "bounce_walk_box_tests_per_ray": round(s2["box_tests"] / t2, 2),
+                      "bounce_walk_prim_tests_per_ray": round(s2["prim_tests"] / t2, 2)},
+        "direct_traced_grays_per_s": round(td / (t_direct * 1e-3) / 1e9, 4),
         "direct_roofline": direct_roof,
     }
 

@@ -438,6 +438,69 @@ __device__ inline void sum_records(const TransferArgs& a, const int2* rec, int c
     }
 }
 
+// sum_records with the loads of U records (record, albedo, direct transfer)
+// issued together before their FMAs, which run in the same order: the same
+// sums, for the pass that reads every record back from the arena.
+template <int K, int U>
+__device__ inline void sum_records_batched(const TransferArgs& a, const int2* rec, int cnt, int D, bool valid,
+                                           int part, int orig, float scale)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    float acc[3][K];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[ch][k] = 0.0f;
+    for (int q0 = 0; q0 < cnt; q0 += U) {
+        int2 e[U];
+        float4 rho[U];
+        float tv[U][K];
+#pragma unroll
+        for (int u = 0; u < U; ++u) e[u] = q0 + u < cnt ? rec[q0 + u] : make_int2(0, 0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = e[u].x;
+            rho[u] = a.albedo_sorted[r];
+            if constexpr (K % 4 == 0) {
+                const float4* td = reinterpret_cast<const float4*>(a.tdir_sorted + (size_t)r * K);
+#pragma unroll
+                for (int k4 = 0; k4 < K / 4; ++k4) {
+                    const float4 v = td[k4];
+                    tv[u][4 * k4] = v.x;
+                    tv[u][4 * k4 + 1] = v.y;
+                    tv[u][4 * k4 + 2] = v.z;
+                    tv[u][4 * k4 + 3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < K; ++k) tv[u][k] = a.tdir_sorted[(size_t)r * K + k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (q0 + u < cnt) {
+                const float w = __int_as_float(e[u].y);
+                const float r0 = rho[u].x * w, r1 = rho[u].y * w, r2 = rho[u].z * w;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    acc[0][k] = fmaf(r0, tv[u][k], acc[0][k]);
+                    acc[1][k] = fmaf(r1, tv[u][k], acc[1][k]);
+                    acc[2][k] = fmaf(r2, tv[u][k], acc[2][k]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float* out = a.partial + (((size_t)part * a.n + orig) * 3 + ch) * K;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float v = segment_sum(acc[ch][k], D) * scale;
+            if (valid && (lane % D) == 0) out[k] += v;
+        }
+    }
+}
+
 // Exclusive prefix sum of v over the lanes of the wave.
 __device__ inline int lane_prefix(int v)
 {
@@ -857,6 +920,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceW
 // wave per work item, its blocks in the order the walk wrote them, each
 // lane's records in blend order (sum_records, the arithmetic of the two-walk
 // blend).  Deferred items are left to the two-walk pass.
+constexpr int kAccBatch = 4;   // records whose loads the record sums issue together
 template <int K>
 __global__ __launch_bounds__(kBlock) void accumulate_kernel(TransferArgs a)
 {
@@ -877,7 +941,7 @@ __global__ __launch_bounds__(kBlock) void accumulate_kernel(TransferArgs a)
             const uint64_t* blk = a.rec + at;
             const int cnt = reinterpret_cast<const uint16_t*>(blk + 1)[lane];
             const int2* rec = reinterpret_cast<const int2*>(blk + kRecHeaderWords) + lane_prefix(cnt);
-            sum_records<K>(a, rec, cnt, D, valid, part, orig, scale);
+            sum_records_batched<K, kAccBatch>(a, rec, cnt, D, valid, part, orig, scale);
             const uint64_t nx = blk[0];
             at = nx == ~0ull ? -1 : (int64_t)nx;
         }
