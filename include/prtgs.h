@@ -105,7 +105,9 @@ typedef struct {
      * direct transfer exists.  Work whose records do not fit is redone by the
      * two-walk method (PRTGS_FLAG_RECORDS_DEFERRED); the results agree with the
      * two-walk method to the last bits of the visibility products.  0 = two
-     * walks (no arena). */
+     * walks (no arena).  With PRTGS_BOUNCE_INDEX any value > 0 makes the walk
+     * that builds the index matrix give the visibility too (no direct pass, no
+     * arena: it keeps only each ray's chosen hit). */
     int64_t bounce_records;
 } prtgs_transfer_desc;
 

@@ -89,6 +89,11 @@ bool one_walk(const prtgs_transfer_desc& d)
 {
     return d.bounces == 1 && d.bounce_mode == PRTGS_BOUNCE_BLEND && d.bounce_records > 0;
 }
+// So does the index matrix, on the same switch (it keeps no records: no arena).
+bool one_walk_index(const prtgs_transfer_desc& d)
+{
+    return d.bounces >= 1 && d.bounce_mode == PRTGS_BOUNCE_INDEX && d.bounce_records > 0;
+}
 
 struct TransferWs {
     size_t dirs, Y, dir_order, rayw, tdir, albedo, tcut, queue, hitkey, hitalpha, hitrec, partial, index, term0, term1,
@@ -341,15 +346,23 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g, const void* bvh
     if (count == 0) return ok();
     TransferArgs a = transfer_args(g, bvh, d, first, count, transfer, vis, w, W);
     if (one_walk(*d)) return hip_status(launch_transfer_fused(a, stream), "one-walk blended bounce");
-    e = launch_transfer_direct(a, stream);
-    if (e != hipSuccess) return hip_status(e, "direct transfer");
-    if (d->bounces > 0 && d->bounce_mode == PRTGS_BOUNCE_BLEND) {
-        e = launch_transfer_bounce(a, stream);
-        if (e != hipSuccess) return hip_status(e, "bounce transfer");
-    } else if (d->bounces > 0) {
+    if (one_walk_index(*d)) {
         a.index = reinterpret_cast<int32_t*>(w + W.index);
-        e = launch_transfer_index(a, stream);
-        if (e != hipSuccess) return hip_status(e, "index matrix");
+        e = launch_index_fused(a, stream, true);
+        if (e != hipSuccess) return hip_status(e, "one-walk index matrix");
+    } else {
+        e = launch_transfer_direct(a, stream);
+        if (e != hipSuccess) return hip_status(e, "direct transfer");
+        if (d->bounces > 0 && d->bounce_mode == PRTGS_BOUNCE_BLEND) {
+            e = launch_transfer_bounce(a, stream);
+            if (e != hipSuccess) return hip_status(e, "bounce transfer");
+        } else if (d->bounces > 0) {
+            a.index = reinterpret_cast<int32_t*>(w + W.index);
+            e = launch_transfer_index(a, stream);
+            if (e != hipSuccess) return hip_status(e, "index matrix");
+        }
+    }
+    if (d->bounces > 0 && d->bounce_mode == PRTGS_BOUNCE_INDEX) {
         // T^m from T^(m-1) by gathers; T^0 is the direct transfer the output
         // already holds in all three channels
         const int K = a.K;
@@ -392,9 +405,11 @@ prtgs_status prtgs_index_matrix(const prtgs_gaussians* g, const void* bvh, const
     a.tdir_sorted = nullptr;   // the walk needs neither the sorted transfers nor the albedo
     a.albedo = nullptr;
     a.albedo_sorted = nullptr;
+    a.index = index;
+    // one walk: the index matrix with the visibility (into scratch), no projection
+    if (one_walk_index(di)) return hip_status(launch_index_fused(a, stream, false), "one-walk index matrix");
     e = launch_transfer_direct(a, stream);
     if (e != hipSuccess) return hip_status(e, "direct transfer");
-    a.index = index;
     return hip_status(launch_transfer_index(a, stream), "index matrix");
 }
 

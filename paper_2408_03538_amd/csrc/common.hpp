@@ -182,6 +182,8 @@ hipError_t launch_transfer_direct(const TransferArgs& a, hipStream_t stream, uns
 hipError_t launch_transfer_bounce(const TransferArgs& a, hipStream_t stream);
 // the blended bounce in one walk per ray: visibility, projection and bounce (needs the arena)
 hipError_t launch_transfer_fused(const TransferArgs& a, hipStream_t stream);
+// the index matrix in one walk per ray (its visibility with it), then, if project, the direct transfer
+hipError_t launch_index_fused(const TransferArgs& a, hipStream_t stream, bool project);
 // the one walk with its work tallied into stats[8] (visibility and records not kept)
 hipError_t launch_fused_stats(const TransferArgs& a, hipStream_t stream, unsigned long long* stats);
 hipError_t launch_transfer_index(const TransferArgs& a, hipStream_t stream);

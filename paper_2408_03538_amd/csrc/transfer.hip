@@ -821,8 +821,9 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                             started = true;
                             ++got;
                             // no later hit can outweigh the best one: its W_j <= T_j <= T
-                            // (each FP32 product by a factor <= 1 stays <= T)
-                            if (T < hp.T_eps || T <= bestW) done = true;
+                            // (each FP32 product by a factor <= 1 stays <= T); the one walk
+                            // goes on for the ray's visibility
+                            if (T < hp.T_eps || (!kFused && T <= bestW)) done = true;
                         } else if (!kIndex && more && !done && bk[q] != kNoHit) {
                             // the hit's weight, summed into the transfer after the selection
                             lrec[nrec] = make_int2(key_j(bk[q]), __float_as_int(ba[q] * T * wc));
@@ -844,7 +845,7 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                 // the source's transfer (the D lanes of a source summed
                 // first).  The sums live only here, not across the selection
                 // or the traversal, which keeps both free of spills.
-                if constexpr (kFused) {
+                if constexpr (kFused && !kIndex) {
                     if constexpr (!kCount) emit_records(a, lrec, nrec, item, prev_block, item_def);
                 } else if constexpr (!kIndex) {
                     sum_records<K>(a, lrec, nrec, D, valid, part, orig, scale);
@@ -901,6 +902,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceW
     TransferArgs a, unsigned long long* stats)
 {
     bounce_walk<K, false, 4, true>(a, stats);
+}
+// the index matrix in one walk per ray (visibility and index, no records)
+template <int K>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kIndexWavesPerSimd))) void fused_index_kernel(
+    TransferArgs a)
+{
+    bounce_walk<K, true, 4, false, true>(a);
 }
 // the blend in one walk per ray, and the same with its work tallied
 template <int K>
@@ -1117,7 +1125,38 @@ hipError_t launch_fused_k(const TransferArgs& a, hipStream_t stream, unsigned lo
     return hipGetLastError();
 }
 
+// The index matrix in one walk per ray (the visibility with it), then, for a
+// transfer, the projection.
+template <int K>
+hipError_t launch_index_fused_k(const TransferArgs& a, hipStream_t stream, bool project)
+{
+    hipError_t e = fill_u32(a.queue, 0u, 1, stream);
+    if (e != hipSuccess) return e;
+    TransferArgs b = a;
+    b.Q = direction_parts(a.G, a.S, a.Q_req);
+    const int64_t items = (int64_t)((a.count + a.G - 1) / a.G) * b.Q;
+    const int cap = bounce_waves(a.n, true);
+    const int waves = items < cap ? (int)items : cap;
+    hipLaunchKernelGGL(fused_index_kernel<K>, dim3((waves + kBlock / kWave - 1) / (kBlock / kWave)), dim3(kBlock), 0,
+                       stream, b);
+    if ((e = hipGetLastError()) != hipSuccess || !project) return e;
+    hipLaunchKernelGGL(project_kernel<K>, dim3((a.count + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_index_fused(const TransferArgs& a, hipStream_t stream, bool project)
+{
+    if (a.count <= 0) return hipSuccess;
+    switch (a.K) {
+        case 1: return launch_index_fused_k<1>(a, stream, project);
+        case 4: return launch_index_fused_k<4>(a, stream, project);
+        case 9: return launch_index_fused_k<9>(a, stream, project);
+        case 16: return launch_index_fused_k<16>(a, stream, project);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_transfer_fused(const TransferArgs& a, hipStream_t stream)
 {

@@ -193,3 +193,35 @@ def test_one_walk_work_counts(prt):
     assert one["box_tests"] < two["box_tests"] + direct["box_tests"]
     _say(f"box tests per ray: one walk {one['box_tests'] / one['traced_rays']:.1f}, two walks "
          f"{two['box_tests'] / two['traced_rays']:.1f} + {direct['box_tests'] / direct['traced_rays']:.1f}")
+
+
+@pytest.mark.parametrize("S,shape", [(64, None), (512, (16, 64))])
+def test_one_walk_index_matrix(prt, oracle_mod, S, shape):
+    """The paper's index matrix in one walk (bounce_records > 0: the walk
+    that picks each ray's hit also yields its visibility; no direct pass, no
+    arena).  Against the oracle on every sampled ray it marks unambiguous,
+    against the two-walk matrix on every ray (they differ only where a
+    visibility product rounds across T_eps), and the transfer with 3 gather
+    bounces against the two-walk one wherever the two matrices agree."""
+    scene = as_f32(_small_million_like(27) if shape is None else _million_recipe(1600, 320, 41))
+    n = scene["means"].shape[0]
+    sc = prt.Scene.from_arrays(scene)
+    bvh = prt.build_bvh(sc, check=True)
+    kw = {} if shape is None else dict(sources_per_wave=shape[0], direction_parts=shape[1])
+    p1 = prt.TransferParams(num_dirs=S, sh_bands=4, bounce_mode="index", bounces=3, bounce_records=1, **kw)
+    p2 = prt.TransferParams(num_dirs=S, sh_bands=4, bounce_mode="index", bounces=3, **kw)
+    idx1 = prt.index_matrix(sc, bvh, p1, check=True).cpu().numpy()
+    idx2 = prt.index_matrix(sc, bvh, p2, check=True).cpu().numpy()
+    differ = idx1 != idx2
+    assert differ.mean() < 1e-3
+    src = np.random.default_rng(44).choice(n, 24, replace=False)
+    _say(f"one-walk index matrix S = {S}: oracle on 24 sources")
+    ref_idx, amb = oracle_mod.index_matrix(scene, S, sources=src)
+    assert np.array_equal(idx1[src][~amb], ref_idx[~amb])
+    t1, _, _ = _run(prt, sc, bvh, p1)
+    t2, _, _ = _run(prt, sc, bvh, p2)
+    same = ~differ.any(axis=1)
+    assert same.mean() > 0.99
+    assert np.abs(t1 - t2)[same].max() <= 1e-4
+    _say(f"one-walk index matrix S = {S}: {differ.sum()} of {differ.size} entries differ from two walks; "
+         f"max |dt| where they agree {np.abs(t1 - t2)[same].max():.2e}")
