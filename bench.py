@@ -5,18 +5,22 @@ A step is one pass of the hot path over the million-splat workload (a unit
 sphere on a 4x4 plane with 200,000 surface splats plus 20 ellipsoid shells of
 40,000 splats each: 1,000,000 Gaussians, S = 512 directions, 16 SH
 coefficients, RGB transfer with one interreflection bounce): BVH build, the
-direct pass, the bounce pass and relighting under one light.  `value` is
-nominal rays (N * S) per second of the whole step, inputs already resident on
-the GPU.  The same JSON line carries the per-pass breakdown, the roofline of
-the dominant kernel (the bounce walk), and the secondary measurements: the
-100k-splat surface workload (direct transfer only), the paper's index-matrix
-bounce, a relit 1080p frame, glossy matrices, relighting 3M splats x 64
-lights with FP32 vs BF16 / F16 storage, forward vs forward + backward on 200k
-splats, and the CPU oracle baseline.
+transfer (one walk per ray gives each ray's visibility and blends its hits;
+the blended hits' records wait in a workspace arena until every direct
+transfer exists) and relighting under one light.  `value` is nominal rays
+(N * S) per second of the whole step, inputs already resident on the GPU.
+The same JSON line carries the breakdown, the roofline of the transfer call
+(the step's dominant work), the same transfer as two walks (direct pass, then
+bounce walk) for comparison, and the secondary measurements: the 100k-splat
+surface workload (direct transfer only), the paper's index-matrix bounce, a
+relit 1080p frame, glossy matrices, relighting 3M splats x 64 lights with FP32
+vs BF16 / F16 storage, forward vs forward + backward on 200k splats, and the
+CPU oracle baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
     python bench.py --copy-mib M      # plain device copy (counter calibration)
-    python bench.py --million-only    # the headline step alone (for profiling)
+    python bench.py --million-only    # the headline step alone (for profiling; --two-walks: as two walks)
+    python bench.py --index-only      # the million-splat index matrix (--two-walks: direct pass + index walk)
     python bench.py --frame-only      # relit 1080p frames of the million-splat scene
     python bench.py --relight-only    # the 3M x 64 relight alone
 """
@@ -96,6 +100,8 @@ def parse():
                     help="only time the 3M x 64 relight in FP32, BF16 and F16 storage")
     ap.add_argument("--surface-only", action="store_true",
                     help="only the 100k surface workload (direct transfer; profiling runs)")
+    ap.add_argument("--two-walks", action="store_true",
+                    help="with --index-only or --million-only: the direct pass and the walk as two walks")
     ap.add_argument("--index-only", action="store_true",
                     help="only the million-splat index matrix (the paper's bounce; profiling runs)")
     return ap.parse_args()
@@ -183,7 +189,8 @@ def main():
     one_walk_stats = None
     if args.index_only:
         bvh = prt.build_bvh(sc)
-        p_idx = prt.TransferParams(num_dirs=S, sh_bands=params.sh_bands, bounce_mode="index", bounces=1)
+        p_idx = prt.TransferParams(num_dirs=S, sh_bands=params.sh_bands, bounce_mode="index", bounces=1,
+                                   bounce_records=0 if args.two_walks else 1)
         ws = prt.Workspace()
         for _ in range(max(1, args.steps)):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -191,12 +198,18 @@ def main():
             idx = prt.index_matrix(sc, bvh, p_idx, workspace=ws)
             b.record()
             torch.cuda.synchronize()
-            log(f"index matrix (direct pass + index walk): {a.elapsed_time(b):.1f} ms")
+            log(f"index matrix ({'direct pass + index walk' if args.two_walks else 'one walk'}): "
+                f"{a.elapsed_time(b):.1f} ms")
             del idx
         return
     # the blend in one walk per ray: its records' arena sized from a counted walk
-    one_walk_stats, params.bounce_records = record_arena(prt, torch, sc, params)
-    log(f"record arena: {params.bounce_records / 1e9:.2f}e9 words ({8 * params.bounce_records / 1e9:.1f} GB)")
+    if args.two_walks:
+        if not args.million_only:
+            raise SystemExit("--two-walks times the million-splat step only with --million-only or --index-only")
+        params.bounce_records = 0
+    else:
+        one_walk_stats, params.bounce_records = record_arena(prt, torch, sc, params)
+        log(f"record arena: {params.bounce_records / 1e9:.2f}e9 words ({8 * params.bounce_records / 1e9:.1f} GB)")
     res = time_steps(prt, torch, np, sc, params, light, args.steps, args.warmup)
     ms_step = res["ms_step"]
     log(f"step {ms_step:.1f} ms: build {res['build']:.2f} ms, transfer {res['transfer']:.1f} ms, "
@@ -444,11 +457,14 @@ def bench_million_extras(prt, torch, scenegen, np, sc, bvh, params, light, trans
     """On the million-splat scene: the paper's own bounce (index matrix, then
     3 bounces by gathers), a relit 1080p frame, glossy matrices at S = 512."""
     out_d = {}
-    p_idx = prt.TransferParams(num_dirs=params.num_dirs, sh_bands=params.sh_bands, bounce_mode="index", bounces=3)
+    # one walk per ray (the index matrix with the visibility), and the two-walk form beside it
+    p_idx = prt.TransferParams(num_dirs=params.num_dirs, sh_bands=params.sh_bands, bounce_mode="index", bounces=3,
+                               bounce_records=1)
+    p_two = prt.TransferParams(**{**p_idx.__dict__, "bounce_records": 0})
     out3 = torch.zeros((sc.n, 3, params.K), dtype=torch.float32, device="cuda")
     ws3 = prt.Workspace()
     prt.precompute_transfer(sc, bvh, p_idx, out=out3, workspace=ws3)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     ev[0].record()
     prt.precompute_transfer(sc, bvh, p_idx, out=out3, workspace=ws3)
     ev[1].record()
@@ -456,19 +472,27 @@ def bench_million_extras(prt, torch, scenegen, np, sc, bvh, params, light, trans
     ev[2].record()
     prev = prt.self_transfer(sc, p_idx, idx, out3)
     ev[3].record()
+    prt.index_matrix(sc, bvh, p_two, workspace=ws3)
+    ev[4].record()
+    prt.precompute_transfer(sc, bvh, p_two, out=out3, workspace=ws3)
+    ev[5].record()
     torch.cuda.synchronize()
     t_all, t_idx, t_gather = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])
     out_d["index_bounces"] = {
-        "workload": "million, the paper's bounce: index matrix + 3 bounces by gathers",
-        "ms_direct_plus_3_bounces": round(t_all, 2), "ms_direct_plus_index_matrix": round(t_idx, 2),
-        "ms_per_gather_bounce": round(t_gather, 3)}
+        "workload": "million, the paper's bounce: index matrix (one walk per ray, with the visibility) + 3 bounces "
+                    "by gathers",
+        "ms_index_walk_plus_3_bounces": round(t_all, 2), "ms_index_matrix": round(t_idx, 2),
+        "ms_per_gather_bounce": round(t_gather, 3),
+        "two_walks": {"ms_direct_plus_index_matrix": round(ev[3].elapsed_time(ev[4]), 2),
+                      "ms_direct_plus_3_bounces": round(ev[4].elapsed_time(ev[5]), 2)}}
     # algorithmic bytes of one gather bounce: the index rows, normals and
     # outputs, plus one RGB transfer row and albedo per indexed ray
     nidx = int((idx >= 0).sum().item())
     g_bytes = sc.n * (4 * params.num_dirs + 12 + 12 * params.K) + nidx * (12 * params.K + 12)
     out_d["index_bounces"]["indexed_rays"] = nidx
     out_d["index_bounces"]["gather_GBps"] = round(g_bytes / (t_gather * 1e-3) / 1e9, 1)
-    log(f"million index mode: direct + index + 3 bounces {t_all:.0f} ms, one gather bounce {t_gather:.2f} ms")
+    log(f"million index mode: one walk + 3 bounces {t_all:.0f} ms (two walks "
+        f"{ev[4].elapsed_time(ev[5]):.0f} ms), one gather bounce {t_gather:.2f} ms")
     del out3, ws3, idx, prev
     torch.cuda.empty_cache()
     out_d["frame_1080p"] = bench_frame(prt, torch, np, sc, transfer_out, light)
