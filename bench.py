@@ -55,13 +55,15 @@ FLOPS_PER_PRIM_TEST = 70
 # only for the kernel sources they were measured on (hash below), else null.
 # direct: traversal + projection of the 100k surface workload
 # (profiles/direct_kernel_surface100k_hbm_counters.md,
-# profiles/direct_kernel_surface100k_sq_counters.md); bounce: bounce_kernel<16>
-# of the million-splat workload (profiles/bounce_kernel_million_counters.md).
+# profiles/direct_kernel_surface100k_sq_counters.md); one walk: every kernel of
+# the million-splat one-walk transfer call (fused_kernel<16>, accumulate_kernel<16>,
+# project_kernel<16>, add_parts_kernel and the deferred-item pass), summed
+# (profiles/one_walk_million_counters.md).
 MEASURED = {
     "direct_surface100k": {"sources_sha256_16": "014a201dfedefb11", "bytes_per_launch": 7.270e9,
                            "valu_instructions_per_launch": 1.1732e10},
-    "one_walk_million": {"sources_sha256_16": "unmeasured", "bytes_per_launch": None,
-                         "valu_instructions_per_launch": None},
+    "one_walk_million": {"sources_sha256_16": "0c7b45258dd13cf4", "bytes_per_launch": 3.7305e12,
+                         "valu_instructions_per_launch": 1.3732e12},
 }
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
                   "paper_2408_03538_amd/csrc/common.hpp", "paper_2408_03538_amd/csrc/capi.hip"]   # capi: work split
@@ -289,16 +291,16 @@ def roofline_of(kernel, stats, ms, bytes_per_unit, extra_unit_bytes=None, counte
 
 def record_arena(prt, torch, sc, params):
     """Work counts of the one walk (a counted run, outside any timed region)
-    and the record arena they call for: one 8-byte record per blended hit,
-    plus a 17-word block header per (work item, direction batch, round), with
-    5% to spare; what does not fit would be redone by two walks."""
+    and the record arena the library's sizing rule gives for them (one record
+    per blended hit, a block header per work item, direction batch and round,
+    5% to spare)."""
     bvh = prt.build_bvh(sc)
     probe = prt.TransferParams(**{**params.__dict__, "bounce_records": 1})
     st = prt.traversal_stats(sc, bvh, probe)
+    words = prt.record_arena_words(sc, bvh, params, stats=st)
     del bvh
     torch.cuda.empty_cache()
-    blocks = sc.n * params.num_dirs // 64 * st["rounds"] / max(1, st["traced_rays"])
-    return st, int(1.05 * (st["blended_hits"] + 17 * blocks)) + (1 << 20)
+    return st, words
 
 
 def million_breakdown(prt, torch, np, sc, params, res, steps, sb):

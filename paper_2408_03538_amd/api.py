@@ -405,6 +405,20 @@ def traversal_stats(scene: Scene, bvh: Bvh, params: TransferParams, first: int =
     return out
 
 
+def record_arena_words(scene: Scene, bvh: Bvh, params: TransferParams, spare: float = 0.05,
+                       stats: dict | None = None) -> int:
+    """Record arena (8-byte words) for the blended bounce in one walk per ray:
+    one record per blended hit and a 17-word block header per (work item,
+    direction batch, traversal round), counted by a counted walk (or taken
+    from `stats`, the traversal_stats of that walk), plus `spare`.  Work
+    whose records would not fit is redone by two walks, so a smaller arena is
+    slower, never wrong."""
+    probe = TransferParams(**{**params.__dict__, "bounces": 1, "bounce_mode": "blend", "bounce_records": 1})
+    st = stats if stats is not None else traversal_stats(scene, bvh, probe)
+    blocks = scene.n * params.num_dirs // 64 * st["rounds"] / max(1, st["traced_rays"])
+    return int((1.0 + spare) * (st["blended_hits"] + 17 * blocks)) + (1 << 20)
+
+
 def pack(x: torch.Tensor, dtype: str) -> torch.Tensor:
     """float32 -> bf16 / f16 storage with round-to-nearest-even."""
     tdt = {"bf16": torch.bfloat16, "f16": torch.float16}[dtype]

@@ -579,6 +579,10 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
     // the grid is whole blocks: a wave past the lists' capacity has none and
     // leaves before it takes work (no block-wide barrier follows)
     if (wslot >= bounce_waves(a.n, kIndex)) return;
+    // (two-walk pass after a one-walk blend) nothing to redo unless the walk deferred an item
+    if (!kFused && a.item_deferred &&
+        !(__atomic_load_n(a.flags, __ATOMIC_RELAXED) & PRTGS_FLAG_RECORDS_DEFERRED))
+        return;
     // each lane's list is contiguous (entry q at [q]): a lane's appends fill whole cache lines
     uint64_t* const lkey = a.hitkey + (size_t)wslot * M * kWave + (size_t)lane * M;
     float* const lalpha = a.hitalpha + (size_t)wslot * M * kWave + (size_t)lane * M;

@@ -58,7 +58,9 @@ def test_one_walk_parity_sampled(prt, oracle_mod):
     n = scene["means"].shape[0]
     sc = prt.Scene.from_arrays(scene)
     bvh = prt.build_bvh(sc, check=True)
-    t1, vis1, f1 = _run(prt, sc, bvh, _params(prt, S, bands, n * S * 16), want_vis=True)
+    # the library's sizing rule leaves room for every record
+    R = prt.record_arena_words(sc, bvh, _params(prt, S, bands, 0))
+    t1, vis1, f1 = _run(prt, sc, bvh, _params(prt, S, bands, R), want_vis=True)
     assert not f1 & _lib.FLAG_RECORDS_DEFERRED
     src = np.random.default_rng(3).choice(n, 200, replace=False)
     _say("one walk: oracle on 200 sources")
