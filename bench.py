@@ -60,7 +60,7 @@ FLOPS_PER_PRIM_TEST = 70
 # project_kernel<16>, add_parts_kernel and the deferred-item pass), summed
 # (profiles/one_walk_million_counters.md).
 MEASURED = {
-    "direct_surface100k": {"sources_sha256_16": "014a201dfedefb11", "bytes_per_launch": 7.270e9,
+    "direct_surface100k": {"sources_sha256_16": "0c7b45258dd13cf4", "bytes_per_launch": 7.278e9,
                            "valu_instructions_per_launch": 1.1732e10},
     "one_walk_million": {"sources_sha256_16": "0c7b45258dd13cf4", "bytes_per_launch": 3.7305e12,
                          "valu_instructions_per_launch": 1.3732e12},
