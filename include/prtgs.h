@@ -111,7 +111,7 @@ typedef struct {
     int64_t bounce_records;
 } prtgs_transfer_desc;
 
-#define PRTGS_BLEND_PARTS_MAX 8     /* blended bounce: direction parts with sums of their own */
+#define PRTGS_BLEND_PARTS_MAX 64    /* blended bounce: direction parts with sums of their own */
 #define PRTGS_BOUNCE_HIT_LIST 256   /* bounce walk: hits a ray lists per traversal round */
 #define PRTGS_BOUNCE_MAX_ROUNDS 4096 /* bounce walk: traversal rounds per ray (each blends >= 1 hit) */
 
@@ -199,10 +199,11 @@ prtgs_status prtgs_bvh_leaf_order(const void* bvh, int32_t n, int32_t* order /* 
 /* of per-ray weights (2 GiB at 1M x 512); with a bounce also 4 n S bytes   */
 /* of per-ray cut depths and the per-lane hit lists of the persistent      */
 /* waves: min(n, 4096) waves and 768 MiB of lists + 512 MiB of hit records */
-/* + 1536 n bytes of per-part bounce sums (at K = 16) for the blend,        */
-/* min(n, 5120) waves and 960 MiB of lists in index mode.  With             */
-/* bounce_records > 0 also the record arena (8 bounce_records bytes) and 12 */
-/* bytes per work item (at most 8 n items).                                 */
+/* + 12 K Q n bytes of bounce sums for the blend (Q = the direction parts  */
+/* it keeps: 64 by default from 16 sources per wave at S >= 256, 12.3 GB  */
+/* at 1M x 512; fewer parts, fewer bytes), min(n, 5120) waves and 960 MiB */
+/* of lists in index mode.  With bounce_records > 0 also the record arena  */
+/* (8 bounce_records bytes) and 12 bytes per work item (Q per source group). */
 /* ---------------------------------------------------------------------- */
 size_t prtgs_transfer_workspace_bytes(const prtgs_transfer_desc* d /* host */, int32_t n);
 prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g /* host */, const void* bvh,

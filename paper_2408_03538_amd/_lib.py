@@ -19,7 +19,7 @@ FLAG_BAD_INDEX = 0x8
 FLAG_ROUND_CAP = 0x10
 FLAG_RECORDS_DEFERRED = 0x20   # informational: part of a one-walk blend was redone with two walks
 BOUNCE_HIT_LIST = 256     # PRTGS_BOUNCE_HIT_LIST
-BLEND_PARTS_MAX = 8       # PRTGS_BLEND_PARTS_MAX
+BLEND_PARTS_MAX = 64      # PRTGS_BLEND_PARTS_MAX
 NOALLOC_SCRATCH_BYTES = 64 << 20   # PRTGS_NOALLOC_SCRATCH_MIB
 BOUNCE_BLEND = 0
 BOUNCE_INDEX = 1

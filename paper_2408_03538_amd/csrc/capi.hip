@@ -95,13 +95,40 @@ bool one_walk_index(const prtgs_transfer_desc& d)
     return d.bounces >= 1 && d.bounce_mode == PRTGS_BOUNCE_INDEX && d.bounce_records > 0;
 }
 
+// Sources per wave of the group split; 1 selects the fan kernel.  With the
+// direction batches spread over waves a launch holds ~count S / 64 waves
+// whatever G is, so the default is chosen by measurement (S = 256 surface
+// scenes): 16 from 40k sources (50k: 6.2 ms against 6.7 for G = 8; 100k: 16.9
+// against 19.5), 8 from 10k (20k: 1.9 against 2.0 for 16, 2.9 for 2), 4 from
+// 2048 (5k: 0.61 against 0.89 for the fan kernel), the fan kernel below.
+// `requested` (a power of two up to 64, 0 = this default) is the caller's.
+int group_size(int count, int requested)
+{
+    if (requested > 0) return requested;
+    return count >= 40000 ? 16 : count >= 10000 ? 8 : count >= 2048 ? 4 : 1;
+}
+
+// The blend's buffers: its direction parts (each with a [n][3][K] set of
+// sums) and, for one walk, its work items (part, source group).  A bounce
+// covers the whole scene (first = 0, count = n), so the launch takes its
+// group size from n as this does.
+struct BlendNeed {
+    int parts;
+    int64_t items;
+};
+
+BlendNeed blend_need(const prtgs_transfer_desc& d, int n)
+{
+    const int G = group_size(n, d.sources_per_wave);
+    const int Q = blend_parts(G, d.num_dirs, d.direction_parts);
+    return {Q, (int64_t)((n + G - 1) / G) * Q};
+}
+
 struct TransferWs {
     size_t dirs, Y, dir_order, rayw, tdir, albedo, tcut, queue, hitkey, hitalpha, hitrec, partial, index, term0, term1,
         rec_top, item_head, item_deferred, rec, total;
     int64_t items;   // one-walk blend: work items (direction part, source group)
 };
-
-int group_size(int count, int requested);
 
 TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
 {
@@ -132,8 +159,9 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     if (d.bounces) off += align256((size_t)bounce_waves(n, idx) * kHitList * 64 * 4);
     w.hitrec = off;
     if (d.bounces && !idx) off += align256((size_t)bounce_waves(n, false) * kHitList * 64 * 8);
+    const BlendNeed need = d.bounces && !idx ? blend_need(d, n) : BlendNeed{0, 0};
     w.partial = off;
-    if (d.bounces && !idx) off += align256(sizeof(float) * kBlendPartsMax * 3 * (size_t)K * (size_t)n);
+    off += align256(sizeof(float) * need.parts * 3 * (size_t)K * (size_t)n);
     w.index = off;
     if (idx) off += align256(sizeof(int32_t) * (size_t)n * (size_t)d.num_dirs);
     w.term0 = off;
@@ -142,10 +170,7 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     if (idx) off += align256(sizeof(float) * 3 * (size_t)K * (size_t)n);
     // one-walk blend: the record arena and per work item its first block and deferral mark
     const bool fused = one_walk(d);
-    const int G = group_size(n, d.sources_per_wave);
-    w.items = fused ? (int64_t)((n + G - 1) / G) * std::min(direction_parts(G, d.num_dirs, d.direction_parts),
-                                                               kBlendPartsMax)
-                    : 0;
+    w.items = fused ? need.items : 0;
     w.rec_top = off;
     if (fused) off += 256;
     w.item_head = off;
@@ -156,19 +181,6 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     if (fused) off += align256(8 * (size_t)d.bounce_records);
     w.total = off;
     return w;
-}
-
-// Sources per wave of the group split; 1 selects the fan kernel.  With the
-// direction batches spread over waves a launch holds ~count S / 64 waves
-// whatever G is, so the default is chosen by measurement (S = 256 surface
-// scenes): 16 from 40k sources (50k: 6.2 ms against 6.7 for G = 8; 100k: 16.9
-// against 19.5), 8 from 10k (20k: 1.9 against 2.0 for 16, 2.9 for 2), 4 from
-// 2048 (5k: 0.61 against 0.89 for the fan kernel), the fan kernel below.
-// `requested` (a power of two up to 64, 0 = this default) is the caller's.
-int group_size(int count, int requested)
-{
-    if (requested > 0) return requested;
-    return count >= 40000 ? 16 : count >= 10000 ? 8 : count >= 2048 ? 4 : 1;
 }
 
 HitParams hit_params(const prtgs_transfer_desc& d)

@@ -212,6 +212,14 @@ inline int direction_parts(int G, int S, int requested)
     return std::max(std::min(Q, batches), 1);
 }
 
+// Direction parts of the blended bounce: each keeps sums of its own (a
+// [Q][n][3][K] buffer added in part order at the end), so the count is capped
+// by kBlendPartsMax.
+inline int blend_parts(int G, int S, int requested)
+{
+    return std::min(direction_parts(G, S, requested), kBlendPartsMax);
+}
+
 // Persistent waves of the bounce launch for n sources (any group size): as
 // many as the 1024 SIMDs hold at the kernel's occupancy; the hit-list scratch
 // holds this many waves.

@@ -1063,10 +1063,8 @@ hipError_t launch_bounce_k(const TransferArgs& a, hipStream_t stream, unsigned l
     hipError_t e = fill_u32(a.queue, 0u, 1, stream);
     if (e != hipSuccess) return e;
     TransferArgs b = a;
-    b.Q = direction_parts(a.G, a.S, a.Q_req);
+    b.Q = kIndex ? direction_parts(a.G, a.S, a.Q_req) : blend_parts(a.G, a.S, a.Q_req);
     if constexpr (!kIndex) {
-        // the blend keeps a set of sums per part: at most kBlendPartsMax parts
-        b.Q = std::min(b.Q, kBlendPartsMax);
         e = fill_u32(reinterpret_cast<uint32_t*>(b.partial), 0u, (size_t)b.Q * a.n * 3 * a.K, stream);
         if (e != hipSuccess) return e;
     }
@@ -1097,7 +1095,7 @@ template <int K>
 hipError_t launch_fused_k(const TransferArgs& a, hipStream_t stream, unsigned long long* stats)
 {
     TransferArgs b = a;
-    b.Q = std::min(direction_parts(a.G, a.S, a.Q_req), kBlendPartsMax);
+    b.Q = blend_parts(a.G, a.S, a.Q_req);
     const int64_t items = (int64_t)((a.count + a.G - 1) / a.G) * b.Q;
     hipError_t e = fill_u32(a.queue, 0u, 1, stream);
     if (e == hipSuccess) e = fill_u32(reinterpret_cast<uint32_t*>(a.rec_top), 0u, 2, stream);

@@ -132,12 +132,14 @@ def test_index_mode_workspace(lib):
     b = lib.prtgs_transfer_workspace_bytes(ctypes.byref(blend), 1000)
     i = lib.prtgs_transfer_workspace_bytes(ctypes.byref(index), 1000)
     lists = 1000 * 256 * 64 * (8 + 4)
-    assert b >= d + lists + 1000 * 256 * 64 * 8 + 8 * 1000 * 3 * 9 * 4   # hit lists + records + part sums
+    # hit lists + records + part sums (1000 sources: one per wave, S = 64 in one part)
+    assert b >= d + lists + 1000 * 256 * 64 * 8 + 1 * 1000 * 3 * 9 * 4
     assert i >= d + lists + 1000 * 64 * 4 + 2 * 1000 * 3 * 9 * 4   # hit lists + index matrix + two bounce terms
     assert i < d + lists + 1000 * 256 * 64 * 8                  # no hit records
     # past 4096 sources the blend's lists and records hold 4096 persistent waves
     # (4 per SIMD), the index mode's lists 5120 (5 per SIMD); the blend also
-    # keeps bounce sums for up to 8 direction parts
+    # keeps bounce sums for each of its direction parts (8 sources per wave,
+    # S = 64: 8 parts)
     n = 20000
     d = lib.prtgs_transfer_workspace_bytes(ctypes.byref(direct), n)
     b = lib.prtgs_transfer_workspace_bytes(ctypes.byref(blend), n)
@@ -146,6 +148,24 @@ def test_index_mode_workspace(lib):
     assert b - d - common == align(4096 * 256 * 64 * 8) * 2 + align(4096 * 256 * 64 * 4) + align(8 * n * 3 * 9 * 4)
     assert i - d - common - align(n * 64 * 4) - 2 * align(n * 3 * 9 * 4) == \
         align(5120 * 256 * 64 * 8) + align(5120 * 256 * 64 * 4)
+
+
+def test_blend_parts_workspace(lib):
+    """The blend's bounce sums take 12 K bytes per source and direction part,
+    for the parts the call keeps: 64 from 16 sources per wave at S = 512 by
+    default, fewer when the caller asks for fewer; the index mode keeps none."""
+    from paper_2408_03538_amd import _lib
+    n, K = 40000, 9
+    size = lambda *a: lib.prtgs_transfer_workspace_bytes(ctypes.byref(_lib.TransferDesc(*a)), n)
+    blend = (512, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99, 0, 1.0)
+    assert _lib.BLEND_PARTS_MAX == 64
+    assert size(*blend, 0, 0) == size(*blend, 16, 64)                   # the default: G = 16, 64 parts
+    for parts in (1, 8, 32):
+        assert size(*blend, 16, 64) - size(*blend, 16, parts) == align(64 * n * 3 * K * 4) - align(parts * n * 3 * K * 4)
+    # 4 sources per wave hold 32 batches of 16 directions: no more parts than that
+    assert size(*blend, 4, 64) == size(*blend, 4, 32)
+    index = (512, 3, 0, 1, 3.0, 0.0, 1e-4, 0.0, 0.99, 1, 1.0)
+    assert size(*index, 16, 64) == size(*index, 16, 8)
 
 
 def test_self_transfer_validation(lib):

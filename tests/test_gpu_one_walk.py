@@ -88,7 +88,7 @@ def _million_recipe(n_surface, per_shell, seed):
 
 def test_one_walk_million_launch_shape(prt, oracle_mod):
     """The launch shape of the million-splat workload (16 sources per wave,
-    64 direction parts of which the blend keeps 8, S = 512) on an 8,000-splat
+    64 direction parts, each with sums of its own, S = 512) on an 8,000-splat
     scene of the same recipe: 24 sampled sources against the oracle, every
     source against the two-walk blend."""
     S = 512
