@@ -125,7 +125,7 @@ BlendNeed blend_need(const prtgs_transfer_desc& d, int n)
 }
 
 struct TransferWs {
-    size_t dirs, Y, dir_order, rayw, tdir, albedo, tcut, queue, hitkey, hitalpha, hitrec, partial, index, term0, term1,
+    size_t dirs, Y, dir_order, rayw, hits, tcut, queue, hitkey, hitalpha, hitrec, partial, index, term0, term1,
         rec_top, item_head, item_deferred, rec, total;
     int64_t items;   // one-walk blend: work items (direction part, source group)
 };
@@ -143,10 +143,8 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     off += align256(sizeof(int32_t) * (size_t)d.num_dirs);
     w.rayw = off;
     off += align256(sizeof(float) * (size_t)n * (size_t)d.num_dirs);
-    w.tdir = off;
-    if (d.bounces) off += align256(sizeof(float) * (size_t)K * (size_t)n);
-    w.albedo = off;
-    if (d.bounces) off += align256(sizeof(float) * 4 * (size_t)n);
+    w.hits = off;
+    if (d.bounces) off += align256(sizeof(float) * (size_t)hit_stride(K) * (size_t)n);
     w.tcut = off;
     if (d.bounces) off += align256(sizeof(float) * (size_t)n * (size_t)d.num_dirs);
     w.queue = off;
@@ -292,9 +290,8 @@ TransferArgs transfer_args(const prtgs_gaussians* g, const void* bvh, const prtg
     a.hp = hit_params(*d);
     a.transfer = transfer;
     a.vis = vis;
-    a.tdir_sorted = bounce ? reinterpret_cast<float*>(w + W.tdir) : nullptr;
+    a.hit_table = bounce ? reinterpret_cast<float*>(w + W.hits) : nullptr;
     a.albedo = g->albedo;
-    a.albedo_sorted = bounce ? reinterpret_cast<float4*>(w + W.albedo) : nullptr;
     a.rayw = reinterpret_cast<float*>(w + W.rayw);
     a.tcut = bounce ? reinterpret_cast<float*>(w + W.tcut) : nullptr;
     a.queue = bounce ? reinterpret_cast<unsigned*>(w + W.queue) : nullptr;
@@ -414,9 +411,8 @@ prtgs_status prtgs_index_matrix(const prtgs_gaussians* g, const void* bvh, const
     // direct pass into scratch (its per-ray depths bound the walk), then the walk
     TransferArgs a = transfer_args(g, bvh, &di, 0, n, reinterpret_cast<float*>(w + W.term0), nullptr, w, W);
     a.channels = 1;
-    a.tdir_sorted = nullptr;   // the walk needs neither the sorted transfers nor the albedo
+    a.hit_table = nullptr;   // the walk needs neither the sorted transfers nor the albedo
     a.albedo = nullptr;
-    a.albedo_sorted = nullptr;
     a.index = index;
     // one walk: the index matrix with the visibility (into scratch), no projection
     if (one_walk_index(di)) return hip_status(launch_index_fused(a, stream, false), "one-walk index matrix");
@@ -770,9 +766,8 @@ prtgs_status prtgs_transfer_backward(const prtgs_gaussians* g, const void* bvh, 
     a.fwd.hp = hit_params(*d);
     a.fwd.transfer = nullptr;
     a.fwd.vis = nullptr;
-    a.fwd.tdir_sorted = nullptr;
+    a.fwd.hit_table = nullptr;
     a.fwd.albedo = nullptr;
-    a.fwd.albedo_sorted = nullptr;
     a.fwd.G = group_size(n, d->sources_per_wave);
     a.fwd.Q_req = d->direction_parts;
     a.fwd.flags = flags;

@@ -22,6 +22,17 @@ constexpr int kMaxRounds = PRTGS_BOUNCE_MAX_ROUNDS;     // bounce: traversal rou
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// What the blended bounce gathers for each hit: the hit splat's direct
+// transfer (K floats) and then its albedo (3 floats), in leaf order, each
+// splat padded to a power of two so that a record's gather touches one cache
+// line (K = 16: 32 floats, 128 bytes).
+__host__ __device__ constexpr int hit_stride(int K)
+{
+    int s = 4;
+    while (s < K + 3) s *= 2;
+    return s;
+}
+
 // Internal BVH node: the boxes of both children and their references.  A
 // reference r >= 0 is an internal node, r < 0 the leaf ~r (a leaf rank).
 // a = (L.lo.x, L.lo.y, L.lo.z, L.hi.x)  b = (L.hi.y, L.hi.z, R.lo.x, R.lo.y)
@@ -144,9 +155,8 @@ struct TransferArgs {
     HitParams hp;
     float* transfer;        // [n][C][K]
     float* vis;             // [n][S] or null
-    float* tdir_sorted;     // [n][K] leaf order, or null
+    float* hit_table;       // [n][hit_stride(K)] leaf order (bounce scratch), or null
     const float* albedo;    // [n][3] original order (bounce)
-    float4* albedo_sorted;  // [n] leaf order (bounce scratch), or null
     uint64_t* hitkey;       // bounce: per-lane hit lists of the persistent waves,
     float* hitalpha;        // [wave][64][kHitList] keys (t bits, leaf rank) and alphas
     float* partial;         // blend: [kBlendPartsMax][n][3][K] each direction part's

@@ -214,11 +214,14 @@ __global__ __launch_bounds__(kBlock) void project_kernel(TransferArgs a)
 #pragma unroll
         for (int k = 0; k < K; ++k) out[k] = t[k];
     }
-    if (a.tdir_sorted) {
+    if (a.hit_table) {
+        constexpr int W = hit_stride(K);
+        float* row = a.hit_table + (size_t)rank * W;
 #pragma unroll
-        for (int k = 0; k < K; ++k) a.tdir_sorted[(size_t)rank * K + k] = t[k];
-        a.albedo_sorted[rank] = make_float4(a.albedo[3 * (size_t)orig], a.albedo[3 * (size_t)orig + 1],
-                                            a.albedo[3 * (size_t)orig + 2], 0.0f);
+        for (int k = 0; k < K; ++k) row[k] = t[k];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) row[K + c] = a.albedo[3 * (size_t)orig + c];
+        if constexpr (K % 4 == 0) row[K + 3] = 0.0f;   // the albedo's float4 is read whole
     }
 }
 
@@ -385,6 +388,31 @@ __device__ inline void merge_chunk(uint64_t (&kk)[N], float (&aa)[N], uint64_t (
             if ((i & dist) == 0) cas_pair(bk[i], ba[i], bk[i + dist], ba[i + dist]);
 }
 
+// A hit splat's direct transfer and albedo from the leaf-order hit table
+// (one row of hit_stride(K) floats: float4 loads where K is a multiple of 4).
+template <int K>
+__device__ inline void load_hit(const float* table, int r, float (&tv)[K], float4& rho)
+{
+    constexpr int W = hit_stride(K);
+    const float* row = table + (size_t)r * W;
+    if constexpr (K % 4 == 0) {
+        const float4* v4 = reinterpret_cast<const float4*>(row);
+#pragma unroll
+        for (int k4 = 0; k4 < K / 4; ++k4) {
+            const float4 v = v4[k4];
+            tv[4 * k4] = v.x;
+            tv[4 * k4 + 1] = v.y;
+            tv[4 * k4 + 2] = v.z;
+            tv[4 * k4 + 3] = v.w;
+        }
+        rho = v4[K / 4];
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) tv[k] = row[k];
+        rho = make_float4(row[K], row[K + 1], row[K + 2], 0.0f);
+    }
+}
+
 // Sums a lane's blended-hit records (leaf rank, weight), in blend order, into
 // its source's 3 K bounce sums of direction part `part` (Eq. 20-22, 30-33:
 // rho_j,c w t_dir[j] per record), the D lanes of a source summed first.  One
@@ -403,22 +431,9 @@ __device__ inline void sum_records(const TransferArgs& a, const int2* rec, int c
         const int2 e = rec[q];
         const int r = e.x;
         const float w = __int_as_float(e.y);
-        const float4 rho = a.albedo_sorted[r];
+        float4 rho;
         float tv[K];
-        if constexpr (K % 4 == 0) {
-            const float4* td = reinterpret_cast<const float4*>(a.tdir_sorted + (size_t)r * K);
-#pragma unroll
-            for (int k4 = 0; k4 < K / 4; ++k4) {
-                const float4 v = td[k4];
-                tv[4 * k4] = v.x;
-                tv[4 * k4 + 1] = v.y;
-                tv[4 * k4 + 2] = v.z;
-                tv[4 * k4 + 3] = v.w;
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < K; ++k) tv[k] = a.tdir_sorted[(size_t)r * K + k];
-        }
+        load_hit<K>(a.hit_table, r, tv, rho);
         const float r0 = rho.x * w, r1 = rho.y * w, r2 = rho.z * w;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -460,21 +475,7 @@ __device__ inline void sum_records_batched(const TransferArgs& a, const int2* re
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int r = e[u].x;
-            rho[u] = a.albedo_sorted[r];
-            if constexpr (K % 4 == 0) {
-                const float4* td = reinterpret_cast<const float4*>(a.tdir_sorted + (size_t)r * K);
-#pragma unroll
-                for (int k4 = 0; k4 < K / 4; ++k4) {
-                    const float4 v = td[k4];
-                    tv[u][4 * k4] = v.x;
-                    tv[u][4 * k4 + 1] = v.y;
-                    tv[u][4 * k4 + 2] = v.z;
-                    tv[u][4 * k4 + 3] = v.w;
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < K; ++k) tv[u][k] = a.tdir_sorted[(size_t)r * K + k];
-            }
+            load_hit<K>(a.hit_table, r, tv[u], rho[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -933,6 +934,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceW
 // lane's records in blend order (sum_records, the arithmetic of the two-walk
 // blend).  Deferred items are left to the two-walk pass.
 constexpr int kAccBatch = 4;   // records whose loads the record sums issue together
+
 template <int K>
 __global__ __launch_bounds__(kBlock) void accumulate_kernel(TransferArgs a)
 {

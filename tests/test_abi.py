@@ -144,7 +144,7 @@ def test_index_mode_workspace(lib):
     d = lib.prtgs_transfer_workspace_bytes(ctypes.byref(direct), n)
     b = lib.prtgs_transfer_workspace_bytes(ctypes.byref(blend), n)
     i = lib.prtgs_transfer_workspace_bytes(ctypes.byref(index), n)
-    common = align(n * 9 * 4) + align(n * 16) + align(n * 64 * 4) + 256   # leaf-order transfer, albedo, cut depths, counter
+    common = align(n * 16 * 4) + align(n * 64 * 4) + 256   # leaf-order transfer + albedo (16 floats), cut depths, counter
     assert b - d - common == align(4096 * 256 * 64 * 8) * 2 + align(4096 * 256 * 64 * 4) + align(8 * n * 3 * 9 * 4)
     assert i - d - common - align(n * 64 * 4) - 2 * align(n * 3 * 9 * 4) == \
         align(5120 * 256 * 64 * 8) + align(5120 * 256 * 64 * 4)

@@ -107,26 +107,29 @@ def test_one_walk_million_launch_shape(prt, oracle_mod):
     _say(f"one walk, million shape: max |dt| = {err:.2e}")
 
 
-@pytest.mark.parametrize("fraction", [0.3, 0.0])
-def test_one_walk_deferred_work(prt, fraction):
+@pytest.mark.parametrize("fraction,spw", [(0.3, 0), (0.0, 0), (0.3, 16), (0.3, 2)])
+def test_one_walk_deferred_work(prt, fraction, spw):
     """An arena that holds a fraction of the records (or a single word): the
     items whose blocks do not fit are redone by the two-walk pass
     (PRTGS_FLAG_RECORDS_DEFERRED), and the transfer and visibility equal the
     one walk's with room for every record.  The redone items blend the same
     hits in the same order and sum each round's records in the same order;
     only a ray that needs several traversal rounds could split its hits
-    differently between rounds, and none does here."""
+    differently between rounds, and none does here.  Sources per wave: the
+    default (4 here: 16 lanes per source), 16 (4 lanes) and 2 (32 lanes), so
+    the lane sums of a source take trees of different depths."""
     from paper_2408_03538_amd import _lib
     S, bands = 64, 4
     scene = as_f32(_small_million_like(25))
     n = scene["means"].shape[0]
     sc = prt.Scene.from_arrays(scene)
     bvh = prt.build_bvh(sc, check=True)
-    big = _params(prt, S, bands, n * S * 16)
+    kw = dict(sources_per_wave=spw) if spw else {}
+    big = _params(prt, S, bands, n * S * 16, **kw)
     st = prt.traversal_stats(sc, bvh, big)
     assert st["rounds"] == st["traced_rays"]
     t1, vis1, f1 = _run(prt, sc, bvh, big, want_vis=True)
-    small = _params(prt, S, bands, max(1, int(fraction * st["blended_hits"])))
+    small = _params(prt, S, bands, max(1, int(fraction * st["blended_hits"])), **kw)
     t2, vis2, f2 = _run(prt, sc, bvh, small, want_vis=True)
     assert not f1 & _lib.FLAG_RECORDS_DEFERRED
     assert f2 & _lib.FLAG_RECORDS_DEFERRED
