@@ -83,8 +83,11 @@ struct RayCounts {
 // orders the children (nearer first).  With kOct every ray of the wave lies
 // in octant `oct`.  With kCount the lane's own single-ray work is tallied in
 // `cnt` (the wave stack then also carries, per entry, whether this lane's
-// ray entered that node).
-template <bool kCount, bool kOct, class LeafFn>
+// ray entered that node).  With kEarly the next node's load is issued before
+// the leaf children's Gaussian tests instead of after them, so that the two
+// overlap: a gain for kernels with few waves per SIMD (the bounce walks, 4-5),
+// a small loss where 8 waves already hide the latency (the direct pass).
+template <bool kCount, bool kOct, bool kEarly, class LeafFn>
 __device__ inline void packet_traverse(const Node* __restrict__ nodes, int n, const RayDir& d, float ox, float oy,
                                        float oz, bool& live, float& tlo, float& thi, unsigned* flags, LeafFn&& leaf,
                                        RayCounts* cnt, const float* order_dir, int oct)
@@ -103,17 +106,16 @@ __device__ inline void packet_traverse(const Node* __restrict__ nodes, int n, co
     int stack = 0;           // entry k of the wave's stack lives in lane k
     uint64_t stack_in = 0;   // (kCount) whether this lane's ray entered entry k's node, bit per entry
     int sp = 0;
-    int node = 0;            // root
     bool inside = live;      // (kCount) this lane's ray entered the current node
     // A depth-first walk enters each of the n - 1 internal nodes at most once;
     // the cap (and the reference check) only guard against a malformed tree.
     int budget = n;
+    Node nd = uniform_load(nodes, 0);   // the root
     while (true) {
         if (--budget < 0) {
             raise_flag(flags, PRTGS_FLAG_BAD_TREE);
             break;
         }
-        const Node nd = uniform_load(nodes, node);
         if (kCount) cnt->wave_nodes++;
         // both tests for every lane, no short-circuit: no divergent branch
         bool hl, hr;
@@ -142,19 +144,13 @@ __device__ inline void packet_traverse(const Node* __restrict__ nodes, int n, co
             raise_flag(flags, PRTGS_FLAG_BAD_TREE);
             break;
         }
-        if (any_l && ref_l < 0) {
-            if (kCount && hl && live) cnt->prim_tests++;
-            if (kCount) cnt->wave_leaves++;
-            leaf(~ref_l, hl);
-            any_l = false;
-        }
-        if (any_r && ref_r < 0) {
-            if (kCount && hr && live) cnt->prim_tests++;
-            if (kCount) cnt->wave_leaves++;
-            leaf(~ref_r, hr);
-            any_r = false;
-        }
-        int next;
+        // The leaf children are visited in this step, the walk then goes on
+        // with an internal child or the top of the stack (chosen first, so
+        // that with kEarly its node load overlaps the leaves' tests).
+        const bool leaf_l = any_l && ref_l < 0, leaf_r = any_r && ref_r < 0;
+        if (leaf_l) any_l = false;
+        if (leaf_r) any_r = false;
+        int next = -1;
         if (any_l && any_r) {
             // nearer child first: order by the box centres along order_dir
             float cl = (nd.a.x + nd.a.w) * order_dir[0] + (nd.a.y + nd.b.x) * order_dir[1] +
@@ -182,14 +178,25 @@ __device__ inline void packet_traverse(const Node* __restrict__ nodes, int n, co
         } else if (any_r) {
             next = ref_r;
             if (kCount) inside = hr;
-        } else {
-            if (sp == 0) break;
+        } else if (sp > 0) {
             --sp;
             next = __builtin_amdgcn_readlane(stack, sp);
             if (kCount) inside = (stack_in >> sp) & 1ull;
         }
-        if (__ballot(live) == 0ull) break;
-        node = next;
+        next = uniform_int(next);
+        if (kEarly && next >= 0) nd = uniform_load(nodes, next);
+        if (leaf_l) {
+            if (kCount && hl && live) cnt->prim_tests++;
+            if (kCount) cnt->wave_leaves++;
+            leaf(~ref_l, hl);
+        }
+        if (leaf_r) {
+            if (kCount && hr && live) cnt->prim_tests++;
+            if (kCount) cnt->wave_leaves++;
+            leaf(~ref_r, hr);
+        }
+        if (next < 0 || __ballot(live) == 0ull) break;
+        if (!kEarly) nd = uniform_load(nodes, next);
     }
 }
 

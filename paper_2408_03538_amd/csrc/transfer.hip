@@ -57,15 +57,18 @@ __device__ inline BatchDir batch_dir(const RayDir& d, bool traced)
     return b;
 }
 
-// Traversal with the octant fast path when the batch allows it.
-template <bool kCount, class LeafFn>
+// Traversal with the octant fast path when the batch allows it; kEarly as in
+// packet_traverse (the bounce walks).
+template <bool kCount, bool kEarly = false, class LeafFn>
 __device__ inline void traverse_batch(const TransferArgs& a, const RayDir& d, const BatchDir& bd, float ox, float oy,
                                       float oz, bool& live, float& tlo, float& thi, LeafFn& leaf, RayCounts* cnt)
 {
     if (bd.uniform_oct)
-        packet_traverse<kCount, true>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf, cnt, bd.mean, bd.oct);
+        packet_traverse<kCount, true, kEarly>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf, cnt, bd.mean,
+                                              bd.oct);
     else
-        packet_traverse<kCount, false>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf, cnt, bd.mean, 0);
+        packet_traverse<kCount, false, kEarly>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf, cnt,
+                                               bd.mean, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -760,7 +763,8 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                         }
                     }
                 };
-                traverse_batch<kCount>(a, d, bd, ox, oy, oz, live, tlo, thi, leaf, kCount ? &rc : (RayCounts*)nullptr);
+                traverse_batch<kCount, true>(a, d, bd, ox, oy, oz, live, tlo, thi, leaf,
+                                             kCount ? &rc : (RayCounts*)nullptr);
                 if (kCount && pending) n_listed += cnt;
 
                 int maxcnt = pending ? cnt : 0;
