@@ -60,10 +60,10 @@ FLOPS_PER_PRIM_TEST = 70
 # project_kernel<16>, add_parts_kernel and the deferred-item pass), summed
 # (profiles/one_walk_million_counters.md).
 MEASURED = {
-    "direct_surface100k": {"sources_sha256_16": "b3b2eacc30821d20", "bytes_per_launch": 7.2757e9,
-                           "valu_instructions_per_launch": 1.1732e10},
-    "one_walk_million": {"sources_sha256_16": "b3b2eacc30821d20", "bytes_per_launch": 3.8212e12,
-                         "valu_instructions_per_launch": 1.3735e12},
+    "direct_surface100k": {"sources_sha256_16": "2f5064f0d30d784d", "bytes_per_launch": 7.2838e9,
+                           "valu_instructions_per_launch": 1.0735e10},
+    "one_walk_million": {"sources_sha256_16": "2f5064f0d30d784d", "bytes_per_launch": 3.7784e12,
+                         "valu_instructions_per_launch": 1.3880e12},
 }
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",
                   "paper_2408_03538_amd/csrc/common.hpp", "paper_2408_03538_amd/csrc/capi.hip"]   # capi: work split
