@@ -63,11 +63,11 @@ __device__ inline void traverse_batch(const TransferArgs& a, const RayDir& d, co
                                       float oz, bool& live, float& tlo, float& thi, LeafFn& leaf)
 {
     if (bd.uniform_oct)
-        packet_traverse<false, true, false>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf, nullptr,
-                                            bd.mean, bd.oct);
+        packet_traverse<false, true, kLeavesFirst>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf,
+                                                   nullptr, bd.mean, bd.oct);
     else
-        packet_traverse<false, false, false>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf, nullptr,
-                                             bd.mean, 0);
+        packet_traverse<false, false, kLeavesFirst>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf,
+                                                    nullptr, bd.mean, 0);
 }
 
 template <int K>

@@ -83,11 +83,19 @@ struct RayCounts {
 // orders the children (nearer first).  With kOct every ray of the wave lies
 // in octant `oct`.  With kCount the lane's own single-ray work is tallied in
 // `cnt` (the wave stack then also carries, per entry, whether this lane's
-// ray entered that node).  With kEarly the next node's load is issued before
-// the leaf children's Gaussian tests instead of after them, so that the two
-// overlap: a gain for kernels with few waves per SIMD (the bounce walks, 4-5),
-// a small loss where 8 waves already hide the latency (the direct pass).
-template <bool kCount, bool kOct, bool kEarly, class LeafFn>
+// ray entered that node).
+//
+// kStep orders each step's work; the walk and its results are the same, the
+// kernels around it compile and run best with different orders (measured):
+//   kLeavesFirst  the leaf children's Gaussian tests, then the choice of the
+//                 next node, its load at the top of the next step (adjoint);
+//   kChooseFirst  the choice, the leaves' tests, then the load (direct pass,
+//                 8 waves per SIMD);
+//   kLoadFirst    the choice and the load, then the leaves' tests, which the
+//                 load then overlaps (the bounce walks, 4-5 waves per SIMD,
+//                 which wait on the latency of the dependent node loads).
+enum TraverseStep { kLeavesFirst, kChooseFirst, kLoadFirst };
+template <bool kCount, bool kOct, int kStep, class LeafFn>
 __device__ inline void packet_traverse(const Node* __restrict__ nodes, int n, const RayDir& d, float ox, float oy,
                                        float oz, bool& live, float& tlo, float& thi, unsigned* flags, LeafFn&& leaf,
                                        RayCounts* cnt, const float* order_dir, int oct)
@@ -110,12 +118,15 @@ __device__ inline void packet_traverse(const Node* __restrict__ nodes, int n, co
     // A depth-first walk enters each of the n - 1 internal nodes at most once;
     // the cap (and the reference check) only guard against a malformed tree.
     int budget = n;
-    Node nd = uniform_load(nodes, 0);   // the root
+    int node = 0;   // the root
+    Node nd;
+    if constexpr (kStep != kLeavesFirst) nd = uniform_load(nodes, node);
     while (true) {
         if (--budget < 0) {
             raise_flag(flags, PRTGS_FLAG_BAD_TREE);
             break;
         }
+        if constexpr (kStep == kLeavesFirst) nd = uniform_load(nodes, node);
         if (kCount) cnt->wave_nodes++;
         // both tests for every lane, no short-circuit: no divergent branch
         bool hl, hr;
@@ -144,12 +155,30 @@ __device__ inline void packet_traverse(const Node* __restrict__ nodes, int n, co
             raise_flag(flags, PRTGS_FLAG_BAD_TREE);
             break;
         }
-        // The leaf children are visited in this step, the walk then goes on
-        // with an internal child or the top of the stack (chosen first, so
-        // that with kEarly its node load overlaps the leaves' tests).
-        const bool leaf_l = any_l && ref_l < 0, leaf_r = any_r && ref_r < 0;
-        if (leaf_l) any_l = false;
-        if (leaf_r) any_r = false;
+        // The leaf children are visited in this step; the walk then goes on
+        // with an internal child or the top of the stack.  (The two forms of
+        // the leaf conditions compile differently; each order takes the one
+        // that measured faster for its kernels.)
+        bool leaf_l = false, leaf_r = false;
+        if constexpr (kStep == kLeavesFirst) {
+            if (any_l && ref_l < 0) {
+                if (kCount && hl && live) cnt->prim_tests++;
+                if (kCount) cnt->wave_leaves++;
+                leaf(~ref_l, hl);
+                any_l = false;
+            }
+            if (any_r && ref_r < 0) {
+                if (kCount && hr && live) cnt->prim_tests++;
+                if (kCount) cnt->wave_leaves++;
+                leaf(~ref_r, hr);
+                any_r = false;
+            }
+        } else {
+            leaf_l = any_l && ref_l < 0;
+            leaf_r = any_r && ref_r < 0;
+            if (leaf_l) any_l = false;
+            if (leaf_r) any_r = false;
+        }
         int next = -1;
         if (any_l && any_r) {
             // nearer child first: order by the box centres along order_dir
@@ -178,25 +207,35 @@ __device__ inline void packet_traverse(const Node* __restrict__ nodes, int n, co
         } else if (any_r) {
             next = ref_r;
             if (kCount) inside = hr;
+        } else if (kStep == kLeavesFirst) {
+            if (sp == 0) break;
+            --sp;
+            next = __builtin_amdgcn_readlane(stack, sp);
+            if (kCount) inside = (stack_in >> sp) & 1ull;
         } else if (sp > 0) {
             --sp;
             next = __builtin_amdgcn_readlane(stack, sp);
             if (kCount) inside = (stack_in >> sp) & 1ull;
         }
-        next = uniform_int(next);
-        if (kEarly && next >= 0) nd = uniform_load(nodes, next);
-        if (leaf_l) {
-            if (kCount && hl && live) cnt->prim_tests++;
-            if (kCount) cnt->wave_leaves++;
-            leaf(~ref_l, hl);
+        if constexpr (kStep != kLeavesFirst) {
+            next = uniform_int(next);
+            if (kStep == kLoadFirst && next >= 0) nd = uniform_load(nodes, next);
+            if (leaf_l) {
+                if (kCount && hl && live) cnt->prim_tests++;
+                if (kCount) cnt->wave_leaves++;
+                leaf(~ref_l, hl);
+            }
+            if (leaf_r) {
+                if (kCount && hr && live) cnt->prim_tests++;
+                if (kCount) cnt->wave_leaves++;
+                leaf(~ref_r, hr);
+            }
+            if (next < 0 || __ballot(live) == 0ull) break;
+            if (kStep == kChooseFirst) nd = uniform_load(nodes, next);
+        } else {
+            if (__ballot(live) == 0ull) break;
+            node = next;
         }
-        if (leaf_r) {
-            if (kCount && hr && live) cnt->prim_tests++;
-            if (kCount) cnt->wave_leaves++;
-            leaf(~ref_r, hr);
-        }
-        if (next < 0 || __ballot(live) == 0ull) break;
-        if (!kEarly) nd = uniform_load(nodes, next);
     }
 }
 

@@ -57,18 +57,18 @@ __device__ inline BatchDir batch_dir(const RayDir& d, bool traced)
     return b;
 }
 
-// Traversal with the octant fast path when the batch allows it; kEarly as in
-// packet_traverse (the bounce walks).
-template <bool kCount, bool kEarly = false, class LeafFn>
+// Traversal with the octant fast path when the batch allows it; kStep as in
+// packet_traverse (kChooseFirst: the direct pass, kLoadFirst: the bounce walks).
+template <bool kCount, int kStep = kChooseFirst, class LeafFn>
 __device__ inline void traverse_batch(const TransferArgs& a, const RayDir& d, const BatchDir& bd, float ox, float oy,
                                       float oz, bool& live, float& tlo, float& thi, LeafFn& leaf, RayCounts* cnt)
 {
     if (bd.uniform_oct)
-        packet_traverse<kCount, true, kEarly>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf, cnt, bd.mean,
-                                              bd.oct);
+        packet_traverse<kCount, true, kStep>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf, cnt, bd.mean,
+                                             bd.oct);
     else
-        packet_traverse<kCount, false, kEarly>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf, cnt,
-                                               bd.mean, 0);
+        packet_traverse<kCount, false, kStep>(a.nodes, a.n, d, ox, oy, oz, live, tlo, thi, a.flags, leaf, cnt,
+                                              bd.mean, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -763,7 +763,7 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                         }
                     }
                 };
-                traverse_batch<kCount, true>(a, d, bd, ox, oy, oz, live, tlo, thi, leaf,
+                traverse_batch<kCount, kLoadFirst>(a, d, bd, ox, oy, oz, live, tlo, thi, leaf,
                                              kCount ? &rc : (RayCounts*)nullptr);
                 if (kCount && pending) n_listed += cnt;
 
