@@ -349,7 +349,8 @@ def million_breakdown(prt, torch, np, sc, params, res, steps, sb):
         f"{blended:.1f} blended / {listed:.1f} listed hits, {rounds:.3f} rounds); two walks {t_two:.0f} ms, "
         f"direct pass alone {t_direct:.0f} ms ({d_box:.0f} / {d_prim:.0f} per ray)")
     roof = roofline_of("fused_kernel<16> + project_kernel + accumulate_kernel: the whole one-walk transfer call "
-                       "(visibility, projection, bounce; the walk is ~96% of it), timed around the call",
+                       "(visibility, projection, bounce; the walk is ~92% of it, the record sums ~8%), "
+                       "timed around the call",
                        sb, t_transfer, b_one,
                        {"box_tests": round(b_box, 2), "prim_tests": round(b_prim, 2),
                         "blended_hits": round(blended, 2), "bytes_per_blended_hit": hit_bytes,
