@@ -354,7 +354,10 @@ prtgs_status prtgs_pack(int64_t count, const float* src, void* dst, prtgs_dtype 
 /* light [B][3][K] F32; colour [n][B][3] in out_dtype (F32 or F16).  The    */
 /* 16-bit path runs on MFMA with FP32 accumulation and the light split into */
 /* a high and a low bf16/f16 part, so its error is set by the storage of     */
-/* transfer and colour.  K in {1, 4, 9, 16}, C in {1, 3}, 1 <= B <= 256.      */
+/* transfer and colour.  F32 transfer and colour with K = 4 or 16 and at     */
+/* least 16 lights run on FP32 MFMA (the same FP32 products, summed in       */
+/* another order than the one-thread-per-colour form used otherwise).        */
+/* K in {1, 4, 9, 16}, C in {1, 3}, 1 <= B <= 256.                           */
 /* ---------------------------------------------------------------------- */
 prtgs_status prtgs_relight(int32_t n, int32_t K, int32_t C, const void* transfer, prtgs_dtype t_dtype,
                            int32_t B, const float* light, void* colour, prtgs_dtype out_dtype,

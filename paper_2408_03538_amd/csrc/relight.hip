@@ -252,6 +252,128 @@ __global__ __launch_bounds__(waves_mfma<OUT16>() * kWave) void relight_mfma_kern
     }
 }
 
+// ------------------------------------------------------------------ FP32 MFMA path
+// FP32 transfers and colours on v_mfma_f32_16x16x4_f32, the 16-bit path's
+// output scheme: D = L' T'^T per 16-row tile, lane l ending with
+// D[4 (l / 16) + 0..3][l % 16], written to a wave-private LDS patch and
+// stored as 16-byte pieces of whole rows.  Column tiles are per channel (16
+// lights of one channel), so no MFMA multiplies zeros; a chunk is the three
+// channels' tiles of kChunkLights32 lights, whose row piece (384 bytes) is
+// three whole 128-byte lines.  Contraction: at step s (of K / 4) lane group g
+// takes coefficient (K / 4) g + s, so a lane's transfer and light values for
+// one channel are consecutive floats (one float4 at K = 16).  A block holds
+// the light fragments of a group of 64 lights in LDS; its waves walk row
+// tiles on their own.
+constexpr int kLightsPerGroup32 = 64;
+constexpr int kChunkLights32 = 32;
+
+template <int K, int C>
+__global__ __launch_bounds__(8 * kWave) void relight_mfma32_kernel(int n, const float* __restrict__ T, int B,
+                                                                   const float* __restrict__ L,
+                                                                   float* __restrict__ out)
+{
+    static_assert(K % 4 == 0, "K = 4 or 16");
+    constexpr int kSteps = K / 4;
+    constexpr int kWaves = 8;
+    constexpr int kTiles = 3 * kLightsPerGroup32 / 16;   // 12 per-channel column tiles
+    constexpr int kChunkCols = 3 * kChunkLights32;       // 96
+    constexpr int kPatchStride = kChunkCols + 4;         // floats; padded rows
+    typedef float fsteps __attribute__((ext_vector_type(kSteps)));
+    __shared__ fsteps lf[kTiles][kWave];
+    __shared__ __align__(16) float stage[kWaves][16 * kPatchStride];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wslot = threadIdx.x / kWave;
+    const int g = lane / 16, li = lane % 16;
+    const int cols = 3 * B;
+    const int light0 = blockIdx.y * kLightsPerGroup32;
+    const int group_lights = min(kLightsPerGroup32, B - light0);
+    const int group_blocks = (group_lights + 15) / 16;   // 16-light blocks in the group
+
+    // light fragments: tile m = 3 lb + c holds lights light0 + 16 lb + 0..15 of channel c
+    for (int m = wslot; m < 3 * group_blocks; m += kWaves) {
+        const int lb = m / 3, c = m % 3;
+        const int b = light0 + 16 * lb + li;
+        fsteps v;
+#pragma unroll
+        for (int st = 0; st < kSteps; ++st) v[st] = b < B ? L[((size_t)b * 3 + c) * K + kSteps * g + st] : 0.0f;
+        lf[m][lane] = v;
+    }
+    __syncthreads();
+
+    float* my_stage = stage[wslot];
+    const int ntiles_rows = (n + 15) / 16;
+    const bool vec_ok = (cols % 4) == 0 && (reinterpret_cast<uintptr_t>(out) % 16) == 0;
+    for (int rt = blockIdx.x * kWaves + wslot; rt < ntiles_rows; rt += gridDim.x * kWaves) {
+        const int64_t row = (int64_t)rt * 16 + li;
+        const bool rvalid = row < n;
+        fsteps tf[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (rvalid) {
+                tf[c] = *reinterpret_cast<const fsteps*>(T + ((size_t)row * C + c) * K + kSteps * g);
+            } else {
+#pragma unroll
+                for (int st = 0; st < kSteps; ++st) tf[c][st] = 0.0f;
+            }
+        }
+        const int nrows = (int)min((int64_t)16, (int64_t)n - (int64_t)rt * 16);
+        for (int lb0 = 0; lb0 < group_blocks; lb0 += kChunkLights32 / 16) {
+#pragma unroll
+            for (int j = 0; j < kChunkLights32 / 16; ++j) {
+                if (lb0 + j < group_blocks) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                        const fsteps a = lf[3 * (lb0 + j) + c][lane];
+                        const fsteps bt = tf[C == 3 ? c : 0];
+#pragma unroll
+                        for (int st = 0; st < kSteps; ++st)
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st], bt[st], acc, 0, 0, 0);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) my_stage[li * kPatchStride + 3 * (16 * j + 4 * g + i) + c] = acc[i];
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            const int first_light = light0 + 16 * lb0;
+            const int chunk_cols = 3 * min(kChunkLights32, B - first_light);
+            float* obase = out + (size_t)rt * 16 * cols + (size_t)3 * first_light;
+            if (vec_ok && chunk_cols == kChunkCols) {
+                // 16 rows x 24 pieces of 16 bytes
+                for (int pc = lane; pc < 16 * (kChunkCols / 4); pc += kWave) {
+                    const int r = pc / (kChunkCols / 4), piece = pc % (kChunkCols / 4);
+                    if (r < nrows)
+                        *reinterpret_cast<float4*>(obase + (size_t)r * cols + 4 * piece) =
+                            *reinterpret_cast<const float4*>(my_stage + r * kPatchStride + 4 * piece);
+                }
+            } else {
+                for (int e = lane; e < 16 * chunk_cols; e += kWave) {
+                    const int r = e / chunk_cols, cc = e % chunk_cols;
+                    if (r < nrows) obase[(size_t)r * cols + cc] = my_stage[r * kPatchStride + cc];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+    }
+}
+
+template <int K, int C>
+hipError_t mfma32_launch(int n, const float* T, int B, const float* L, float* out, hipStream_t stream)
+{
+    const int groups = (B + kLightsPerGroup32 - 1) / kLightsPerGroup32;
+    const int row_tiles = (n + 15) / 16;
+    // about 8 waves per SIMD over 256 CUs in all, walking the row tiles
+    int blocks = (256 * 4 * 8 / 8 + groups - 1) / groups;
+    const int need = (row_tiles + 7) / 8;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((relight_mfma32_kernel<K, C>), dim3(blocks, groups), dim3(8 * kWave), 0, stream, n, T, B, L,
+                       out);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ backward
 
 constexpr int kBwdRows = 1024;
@@ -368,6 +490,12 @@ hipError_t relight_kc(int n, const void* T, prtgs_dtype tdt, int B, const float*
                       hipStream_t stream)
 {
     bool out16 = odt == PRTGS_F16;
+    // FP32 on MFMA from one whole 16-light tile up (fewer lights would leave
+    // most of each tile's products zero: the one-column kernel is better there)
+    if constexpr (K % 4 == 0) {
+        if (tdt == PRTGS_F32 && !out16 && B >= 16 && (reinterpret_cast<uintptr_t>(T) % 16) == 0)
+            return mfma32_launch<K, C>(n, static_cast<const float*>(T), B, L, static_cast<float*>(out), stream);
+    }
     if (tdt == PRTGS_F32) return f32_dispatch<K, C>(n, static_cast<const float*>(T), B, L, out, out16, stream);
     if (tdt == PRTGS_BF16) return mfma_dispatch<K, C, true>(n, T, B, L, out, out16, stream);
     return mfma_dispatch<K, C, false>(n, T, B, L, out, out16, stream);
