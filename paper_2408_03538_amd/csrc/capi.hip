@@ -151,12 +151,16 @@ TransferWs transfer_ws_layout(const prtgs_transfer_desc& d, int n)
     if (d.bounces) off += 256;
     // index mode: the index matrix and two bounce terms [n][3][K] (ping-pong)
     const bool idx = d.bounces && d.bounce_mode == PRTGS_BOUNCE_INDEX;
+    // the lists hold the persistent waves of every walk the call may run (one walk: its own and the two-walk
+    // pass over deferred items)
+    const size_t lw = idx ? bounce_waves(n, kWalkIndex)
+                          : std::max(bounce_waves(n, kWalkBlend), one_walk(d) ? bounce_waves(n, kWalkFused) : 0);
     w.hitkey = off;
-    if (d.bounces) off += align256((size_t)bounce_waves(n, idx) * kHitList * 64 * 8);
+    if (d.bounces) off += align256(lw * kHitList * 64 * 8);
     w.hitalpha = off;
-    if (d.bounces) off += align256((size_t)bounce_waves(n, idx) * kHitList * 64 * 4);
+    if (d.bounces) off += align256(lw * kHitList * 64 * 4);
     w.hitrec = off;
-    if (d.bounces && !idx) off += align256((size_t)bounce_waves(n, false) * kHitList * 64 * 8);
+    if (d.bounces && !idx) off += align256(lw * kHitList * 64 * 8);
     const BlendNeed need = d.bounces && !idx ? blend_need(d, n) : BlendNeed{0, 0};
     w.partial = off;
     off += align256(sizeof(float) * need.parts * 3 * (size_t)K * (size_t)n);

@@ -15,7 +15,8 @@ constexpr int kWave = 64;                 // CDNA wavefront width
 constexpr float kBoxSigma = 3.0f;         // BVH boxes enclose the 3-sigma ellipsoid
 constexpr size_t kFlagBytes = 256;        // flag word + padding at the head of a workspace
 constexpr int kHitList = PRTGS_BOUNCE_HIT_LIST;   // bounce: hits listed per ray and round
-constexpr int kBounceWavesPerSimd = 4;    // bounce (blend): resident waves per SIMD
+constexpr int kBounceWavesPerSimd = 4;    // bounce (blend, two walks): resident waves per SIMD
+constexpr int kFusedWavesPerSimd = 5;     // bounce (blend, one walk): resident waves per SIMD
 constexpr int kIndexWavesPerSimd = 5;     // bounce (index matrix): resident waves per SIMD
 constexpr int kBlendPartsMax = PRTGS_BLEND_PARTS_MAX;   // bounce (blend): direction parts with sums of their own
 constexpr int kMaxRounds = PRTGS_BOUNCE_MAX_ROUNDS;     // bounce: traversal rounds per ray
@@ -230,12 +231,15 @@ inline int blend_parts(int G, int S, int requested)
     return std::min(direction_parts(G, S, requested), kBlendPartsMax);
 }
 
-// Persistent waves of the bounce launch for n sources (any group size): as
+// Persistent waves of the bounce launches for n sources (any group size): as
 // many as the 1024 SIMDs hold at the kernel's occupancy; the hit-list scratch
 // holds this many waves.
-__host__ __device__ inline int bounce_waves(int n, bool index)
+enum WalkKind { kWalkBlend, kWalkFused, kWalkIndex };
+__host__ __device__ inline int bounce_waves(int n, int kind)
 {
-    const int cap = 1024 * (index ? kIndexWavesPerSimd : kBounceWavesPerSimd);
+    const int per = kind == kWalkIndex ? kIndexWavesPerSimd : kind == kWalkFused ? kFusedWavesPerSimd
+                                                                                   : kBounceWavesPerSimd;
+    const int cap = 1024 * per;
     return n < cap ? n : cap;
 }
 

@@ -339,7 +339,8 @@ __device__ inline int key_j(uint64_t k) { return (int)(uint32_t)k; }
 // still transparent, traverses again from its last hit.  The launch is
 // persistent: a fixed set of waves takes groups of sources from a counter,
 // so the lists are sized by the waves, not the scene.
-constexpr int kSelBlend = 16;   // hits selected per pass over the list: the blend
+constexpr int kSelBlend = 16;   // hits selected per pass over the list: the blend in two walks,
+constexpr int kSelFused = 8;    // the blend in one walk (its fewer registers let it run 5 waves per SIMD),
 constexpr int kSelIndex = 8;    // and the index walk
 constexpr int kCheck = 8;   // depth checkpoints per ray and round
 
@@ -575,14 +576,15 @@ template <int K, bool kIndex, int kScan, bool kCount = false, bool kFused = fals
 __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long long* stats = nullptr)
 {
     constexpr int M = kHitList;
-    constexpr int kBlend = kIndex ? kSelIndex : kSelBlend;
+    constexpr int kBlend = kIndex ? kSelIndex : kFused ? kSelFused : kSelBlend;
+    constexpr int kKind = kIndex ? kWalkIndex : kFused ? kWalkFused : kWalkBlend;
     const int lane = threadIdx.x & (kWave - 1);
     const int G = a.G;
     const int D = kWave / G;
     const int wslot = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     // the grid is whole blocks: a wave past the lists' capacity has none and
     // leaves before it takes work (no block-wide barrier follows)
-    if (wslot >= bounce_waves(a.n, kIndex)) return;
+    if (wslot >= bounce_waves(a.n, kKind)) return;
     // (two-walk pass after a one-walk blend) nothing to redo unless the walk deferred an item
     if (!kFused && a.item_deferred &&
         !(__atomic_load_n(a.flags, __ATOMIC_RELAXED) & PRTGS_FLAG_RECORDS_DEFERRED))
@@ -921,13 +923,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kIndexWa
 }
 // the blend in one walk per ray, and the same with its work tallied
 template <int K>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceWavesPerSimd))) void fused_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kFusedWavesPerSimd))) void fused_kernel(
     TransferArgs a)
 {
     bounce_walk<K, false, 4, false, true>(a);
 }
 template <int K>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceWavesPerSimd))) void fused_count_kernel(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kFusedWavesPerSimd))) void fused_count_kernel(
     TransferArgs a, unsigned long long* stats)
 {
     bounce_walk<K, false, 4, true, true>(a, stats);
@@ -1075,7 +1077,7 @@ hipError_t launch_bounce_k(const TransferArgs& a, hipStream_t stream, unsigned l
         if (e != hipSuccess) return e;
     }
     const int64_t items = (int64_t)((a.count + a.G - 1) / a.G) * b.Q;
-    const int cap = bounce_waves(a.n, kIndex);   // the hit lists hold this many
+    const int cap = bounce_waves(a.n, kIndex ? kWalkIndex : kWalkBlend);   // the hit lists hold this many
     const int waves = items < cap ? (int)items : cap;
     const dim3 grid((waves + kBlock / kWave - 1) / (kBlock / kWave));
     if constexpr (kIndex) {
@@ -1110,7 +1112,7 @@ hipError_t launch_fused_k(const TransferArgs& a, hipStream_t stream, unsigned lo
     if (e == hipSuccess && !stats)
         e = fill_u32(reinterpret_cast<uint32_t*>(b.partial), 0u, (size_t)b.Q * a.n * 3 * a.K, stream);
     if (e != hipSuccess) return e;
-    const int cap = bounce_waves(a.n, false);
+    const int cap = bounce_waves(a.n, kWalkFused);
     const int waves = items < cap ? (int)items : cap;
     const dim3 grid((waves + kBlock / kWave - 1) / (kBlock / kWave));
     if (stats) {
@@ -1125,7 +1127,10 @@ hipError_t launch_fused_k(const TransferArgs& a, hipStream_t stream, unsigned lo
     hipLaunchKernelGGL(accumulate_kernel<K>, dim3((unsigned)acc_blocks), dim3(kBlock), 0, stream, b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = fill_u32(a.queue, 0u, 1, stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(bounce_kernel<K>, grid, dim3(kBlock), 0, stream, b);
+    const int bcap = bounce_waves(a.n, kWalkBlend);
+    const int bwaves = items < bcap ? (int)items : bcap;
+    hipLaunchKernelGGL(bounce_kernel<K>, dim3((bwaves + kBlock / kWave - 1) / (kBlock / kWave)), dim3(kBlock), 0,
+                       stream, b);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const size_t count = (size_t)a.n * 3 * a.K;
     hipLaunchKernelGGL(add_parts_kernel, dim3((unsigned)std::min<size_t>((count + 255) / 256, 65536)), dim3(256), 0,
@@ -1143,7 +1148,7 @@ hipError_t launch_index_fused_k(const TransferArgs& a, hipStream_t stream, bool 
     TransferArgs b = a;
     b.Q = direction_parts(a.G, a.S, a.Q_req);
     const int64_t items = (int64_t)((a.count + a.G - 1) / a.G) * b.Q;
-    const int cap = bounce_waves(a.n, true);
+    const int cap = bounce_waves(a.n, kWalkIndex);
     const int waves = items < cap ? (int)items : cap;
     hipLaunchKernelGGL(fused_index_kernel<K>, dim3((waves + kBlock / kWave - 1) / (kBlock / kWave)), dim3(kBlock), 0,
                        stream, b);
