@@ -210,8 +210,12 @@ def _scale(T, L):
 
 
 @pytest.mark.parametrize("n,C,K,B", [(5000, 1, 16, 1), (5000, 3, 16, 64), (777, 3, 9, 7), (1000, 1, 4, 100),
-                                     (333, 3, 16, 256), (17, 1, 1, 3)])
+                                     (333, 3, 16, 256), (17, 1, 1, 3), (1001, 3, 16, 18), (513, 1, 4, 33)])
 def test_relight_f32(prt, oracle_mod, n, C, K, B):
+    """FP32 transfer and colours against the FP64 product: the one-thread-per-
+    colour kernel (fewer than 16 lights, K = 1 or 9) and the FP32 MFMA one,
+    with whole 32-light chunks (16-byte row stores) and partial ones or light
+    counts not divisible by 4 (18, 33, the last 4 of 100: element stores)."""
     import torch
     T, L = _relight_inputs(n, C, K, B, 40 + K)
     out = prt.relight(torch.tensor(T, dtype=torch.float32, device="cuda"),
