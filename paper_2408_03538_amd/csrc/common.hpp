@@ -160,8 +160,8 @@ struct TransferArgs {
     const float* albedo;    // [n][3] original order (bounce)
     uint64_t* hitkey;       // bounce: per-lane hit lists of the persistent waves,
     float* hitalpha;        // [wave][64][kHitList] keys (t bits, leaf rank) and alphas
-    float* partial;         // blend: [kBlendPartsMax][n][3][K] each direction part's
-                            // bounce sums, added into transfer in part order
+    float* partial;         // blend: [Q][n][3][K] each direction part's bounce sums
+                            // (Q = blend_parts), added into transfer in part order
     int2* hitrec;           // blend: [wave][64][kHitList] (leaf rank, weight) of the
                             // hits blended in the current round, in blend order
     unsigned* queue;        // bounce: work counter (zeroed before the launch)

@@ -889,12 +889,15 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
     }
 }
 
-// The two modes hold different registers at their peak (the blend its 3K
-// sums, the index mode none), so each gets the occupancy, buffer and scan
-// width that measured fastest: the blend 4 waves per SIMD, a 16-hit buffer
-// and 4 entries per step (fewer passes over the lists than with 8 hits: the
-// million-splat transfer call 3.34 -> 3.29 s), the index walk 5 waves, 8
-// hits and 4 entries (a few cold spills in both).
+// The walks hold different registers at their peak (the two-walk blend its
+// 3K sums, the one-walk blend and the index mode none), so each gets the
+// occupancy, buffer and scan width that measured fastest: the two-walk blend
+// 4 waves per SIMD, a 16-hit buffer and 4 entries per step (fewer passes over
+// the lists than with 8 hits: the million-splat transfer call 3.34 -> 3.29
+// s); the one-walk blend 5 waves and 8 hits (2401 -> 2333 ms: once its node
+// loads overlap the leaf tests, resident waves pay more than fewer passes);
+// the index walk 5 waves, 8 hits; 4 entries per step for all (cold spills in
+// each).
 template <int K>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceWavesPerSimd))) void bounce_kernel(
     TransferArgs a)

@@ -136,7 +136,7 @@ def test_index_mode_workspace(lib):
     assert b >= d + lists + 1000 * 256 * 64 * 8 + 1 * 1000 * 3 * 9 * 4
     assert i >= d + lists + 1000 * 64 * 4 + 2 * 1000 * 3 * 9 * 4   # hit lists + index matrix + two bounce terms
     assert i < d + lists + 1000 * 256 * 64 * 8                  # no hit records
-    # past 4096 sources the blend's lists and records hold 4096 persistent waves
+    # past 4096 sources the two-walk blend's lists and records hold 4096 persistent waves
     # (4 per SIMD), the index mode's lists 5120 (5 per SIMD); the blend also
     # keeps bounce sums for each of its direction parts (8 sources per wave,
     # S = 64: 8 parts)
