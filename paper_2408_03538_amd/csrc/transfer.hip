@@ -638,7 +638,10 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
             if (__ballot(pending) == 0ull) continue;
             const bool traced = pending;
             if (kCount && traced) ++n_traced;
-            const BatchDir bd = batch_dir(d, pending);
+            BatchDir bd = batch_dir(d, pending);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)   // uniform: kept in scalar registers through the walk
+                bd.mean[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(bd.mean[k])));
             const float wc = c * kInvPi;
             // No hit beyond tc can carry weight: the direct pass saw the
             // transmittance fall below T_eps using hits no farther than tc.
@@ -726,7 +729,11 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
                 auto leaf = [&](int r, bool box_hit) {
                     const Prim p = uniform_load(a.prims, r);
                     const PreHit q = gaussian_pre(p, ox, oy, oz, d, hp);
-                    const bool cand = q.maybe & box_hit & live & (r != rank);
+                    // no r != rank test: the ray starts at the source's own mean, so its own
+                    // Gaussian peaks at t* = 0 exactly (a zero offset in both stages) and fails
+                    // t* > t_min >= 0; without the test the lane's rank need not stay in a
+                    // register through the walk (it was spilled and reloaded at every leaf)
+                    const bool cand = q.maybe & box_hit & live;
                     if (__ballot(cand) == 0ull) return;
                     HitResult h;
                     const bool hit = gaussian_exact(p, q, ox, oy, oz, d, hp, h) & cand;
