@@ -199,7 +199,7 @@ prtgs_status prtgs_bvh_leaf_order(const void* bvh, int32_t n, int32_t* order /* 
 /* of per-ray weights (2 GiB at 1M x 512); with a bounce also 4 n S bytes   */
 /* of per-ray cut depths and the per-lane hit lists of the persistent      */
 /* waves: min(n, 4096) waves and 768 MiB of lists + 512 MiB of hit records */
-/* (with bounce_records > 0: min(n, 5120) waves, 960 + 640 MiB)            */
+/* (with bounce_records > 0: min(n, 7168) waves, 1344 + 896 MiB)           */
 /* + 12 K Q n bytes of bounce sums for the blend (Q = the direction parts  */
 /* it keeps: 64 by default from 16 sources per wave at S >= 256, 12.3 GB  */
 /* at 1M x 512; fewer parts, fewer bytes), min(n, 5120) waves and 960 MiB */

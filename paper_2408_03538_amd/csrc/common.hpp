@@ -16,7 +16,7 @@ constexpr float kBoxSigma = 3.0f;         // BVH boxes enclose the 3-sigma ellip
 constexpr size_t kFlagBytes = 256;        // flag word + padding at the head of a workspace
 constexpr int kHitList = PRTGS_BOUNCE_HIT_LIST;   // bounce: hits listed per ray and round
 constexpr int kBounceWavesPerSimd = 4;    // bounce (blend, two walks): resident waves per SIMD
-constexpr int kFusedWavesPerSimd = 5;     // bounce (blend, one walk): resident waves per SIMD
+constexpr int kFusedWavesPerSimd = 7;     // bounce (blend, one walk): resident waves per SIMD
 constexpr int kIndexWavesPerSimd = 5;     // bounce (index matrix): resident waves per SIMD
 constexpr int kBlendPartsMax = PRTGS_BLEND_PARTS_MAX;   // bounce (blend): direction parts with sums of their own
 constexpr int kMaxRounds = PRTGS_BOUNCE_MAX_ROUNDS;     // bounce: traversal rounds per ray

@@ -340,7 +340,7 @@ __device__ inline int key_j(uint64_t k) { return (int)(uint32_t)k; }
 // persistent: a fixed set of waves takes groups of sources from a counter,
 // so the lists are sized by the waves, not the scene.
 constexpr int kSelBlend = 16;   // hits selected per pass over the list: the blend in two walks,
-constexpr int kSelFused = 8;    // the blend in one walk (its fewer registers let it run 5 waves per SIMD),
+constexpr int kSelFused = 8;    // the blend in one walk (its fewer registers let it run 7 waves per SIMD),
 constexpr int kSelIndex = 8;    // and the index walk
 constexpr int kCheck = 8;   // depth checkpoints per ray and round
 
@@ -901,10 +901,11 @@ __device__ __forceinline__ void bounce_walk(const TransferArgs& a, unsigned long
 // occupancy, buffer and scan width that measured fastest: the two-walk blend
 // 4 waves per SIMD, a 16-hit buffer and 4 entries per step (fewer passes over
 // the lists than with 8 hits: the million-splat transfer call 3.34 -> 3.29
-// s); the one-walk blend 5 waves and 8 hits (2401 -> 2333 ms: once its node
-// loads overlap the leaf tests, resident waves pay more than fewer passes);
-// the index walk 5 waves, 8 hits; 4 entries per step for all (cold spills in
-// each).
+// s); the one-walk blend 7 waves and 8 hits (its time is the latency of its
+// dependent loads, so resident waves pay more than fewer passes over the lists
+// or spill traffic: 5 / 6 / 7 / 8 waves 2214 / 2101-2123 / 2093 / 2447 ms at
+// 1M x 512, with 22 / 62 / 68 / 113 VGPRs spilled); the index walk 5 waves, 8
+// hits; 4 entries per step for all.
 template <int K>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBounceWavesPerSimd))) void bounce_kernel(
     TransferArgs a)

@@ -286,7 +286,7 @@ def test_one_walk_workspace(lib):
     """bounce_records (blend, one bounce) adds the record arena (8 bytes a
     word), a 256-byte counter and, per work item (direction part x source
     group), an 8-byte chain head and a 4-byte deferral mark, and its hit lists
-    hold the one walk's 5120 persistent waves (5 per SIMD) instead of the
+    hold the one walk's 7168 persistent waves (7 per SIMD) instead of the
     two-walk kernel's 4096; it is ignored in index mode and without a bounce,
     and a negative size is refused."""
     from paper_2408_03538_amd import _lib
@@ -295,7 +295,7 @@ def test_one_walk_workspace(lib):
     size = lambda *a: lib.prtgs_transfer_workspace_bytes(ctypes.byref(_lib.TransferDesc(*a)), n)
     two, one = size(*args, 0), size(*args, R)
     items = (n + 15) // 16 * 4
-    lists = sum(align(5120 * 256 * 64 * b) - align(4096 * 256 * 64 * b) for b in (8, 4, 8))   # keys, alphas, records
+    lists = sum(align(7168 * 256 * 64 * b) - align(4096 * 256 * 64 * b) for b in (8, 4, 8))   # keys, alphas, records
     assert one - two == 256 + align(8 * items) + align(4 * items) + align(8 * R) + lists
     index = (64, 3, 0, 3, 3.0, 0.0, 1e-4, 0.0, 0.99, 1, 1.0, 16, 4)
     assert size(*index, R) == size(*index, 0)
