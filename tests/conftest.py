@@ -13,6 +13,15 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
 
 
+@pytest.fixture(autouse=True)
+def _live_progress(capsys):
+    """Hands the test's capture fixture to helpers.say for its progress lines."""
+    import helpers
+    helpers._capture = capsys
+    yield
+    helpers._capture = None
+
+
 @pytest.fixture(scope="session")
 def oracle_mod():
     import oracle

@@ -1,5 +1,22 @@
-"""Shared test helpers: FP32 rounding of generated scenes and parity checks."""
+"""Shared test helpers: FP32 rounding of generated scenes, parity checks and
+progress lines."""
 import numpy as np
+
+# pytest's capture fixture of the running test (set by tests/conftest.py), so
+# that progress lines pass the output capture
+_capture = None
+
+
+def say(msg):
+    """Print a progress line at once, also while pytest captures the test's
+    output: a long full-size test would otherwise print nothing until it
+    ends, and a harness that watches the output for silence would take it
+    for hung."""
+    if _capture is not None:
+        with _capture.disabled():
+            print(msg, flush=True)
+    else:
+        print(msg, flush=True)
 
 
 def as_f32(arrays: dict) -> dict:

@@ -7,13 +7,12 @@ hits, the gradient needs the whole forward), properties that hold at any size
 are checked instead.
 """
 import math
-import sys
 
 import numpy as np
 import pytest
 
 import scenegen
-from helpers import as_f32, assert_ray_vis, assert_transfer_parity
+from helpers import as_f32, assert_ray_vis, assert_transfer_parity, say
 
 pytestmark = pytest.mark.gpu
 
@@ -24,11 +23,6 @@ def prt():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     import paper_2408_03538_amd as p
     return p
-
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
 
 
 def _workload_scene(name):
@@ -51,13 +45,13 @@ def _sampled_parity(prt, oracle_mod, what, scene, S, bands, src, allow_share):
     t_s = t[rows, 0, :].cpu().numpy()
     v_s = vis[rows].cpu().numpy()
     del t, vis
-    _say(f"{what}: oracle on {len(src)} sources")
+    say(f"{what}: oracle on {len(src)} sources")
     ref = oracle_mod.direct_transfer(scene, S, bands, sources=src, want_vis=True, want_allow=True, want_vis_bounds=True)
     err = assert_transfer_parity(t_s, ref["t"], ref["allow"])
     cos = scene["normals"][src] @ oracle_mod.directions(S).T
     rays, wide = assert_ray_vis(v_s, ref, cos, oracle_mod.DEFAULT_MARGINS[0], what)
     share = float((ref["allow"] > 1e-4).mean())
-    _say(f"{what}: max |dt| = {err:.2e}; {rays} rays within their range ({wide} near a threshold); coefficients "
+    say(f"{what}: max |dt| = {err:.2e}; {rays} rays within their range ({wide} near a threshold); coefficients "
          f"with allowance > 1e-4: {100 * share:.2f}% (largest {ref['allow'].max():.1e})")
     assert share < allow_share
 
@@ -99,10 +93,10 @@ def test_million_bounce_properties(prt):
     sc = prt.Scene.from_arrays(scene)
     bvh = prt.build_bvh(sc, check=True)
     S, bands = w["num_dirs"], w["bands"]
-    _say("million: direct transfer with visibility")
+    say("million: direct transfer with visibility")
     td, vis = prt.precompute_transfer(sc, bvh, prt.TransferParams(num_dirs=S, sh_bands=bands), want_vis=True,
                                       check=True)
-    _say("million: direct + bounce")
+    say("million: direct + bounce")
     tb = prt.precompute_transfer(sc, bvh, prt.TransferParams(num_dirs=S, sh_bands=bands, bounces=1), check=True)
     assert torch.equal(tb[:, 2], td[:, 0])
     d = td[:, 0].double()
@@ -124,7 +118,7 @@ def test_million_bounce_properties(prt):
     bound = (4 * math.pi / S) * occluded * rho_t.max().item() / math.pi
     got = ind0[rows_t, 0].cpu().numpy()
     assert (got <= bound + 2e-5).all(), float((got - bound).max())
-    _say(f"million bounce: linearity {lin:.1e}, max bounce DC {got.max():.3f} (bound {bound.max():.3f})")
+    say(f"million bounce: linearity {lin:.1e}, max bounce DC {got.max():.3f} (bound {bound.max():.3f})")
 
 
 def test_million_index_sampled_rows(prt, oracle_mod):
@@ -139,11 +133,11 @@ def test_million_index_sampled_rows(prt, oracle_mod):
     bvh = prt.build_bvh(sc, check=True)
     S, bands = w["num_dirs"], w["bands"]
     params = prt.TransferParams(num_dirs=S, sh_bands=bands, bounce_mode="index", bounces=3)
-    _say("million: index matrix")
+    say("million: index matrix")
     idx = prt.index_matrix(sc, bvh, params, check=True)
     rng = np.random.default_rng(106)
     rows = np.concatenate([rng.choice(200_000, 2, replace=False), 200_000 + rng.choice(n - 200_000, 2, replace=False)])
-    _say("million: oracle index rows of 4 sources")
+    say("million: oracle index rows of 4 sources")
     ref, amb = oracle_mod.index_matrix(scene, S, sources=rows)
     got = idx[torch.tensor(rows, device=idx.device)].cpu().numpy()
     assert (ref >= 0).sum() > 20
@@ -151,13 +145,13 @@ def test_million_index_sampled_rows(prt, oracle_mod):
     # rays meet hundreds of Gaussians here, so some choice often hangs on a
     # hit at the 3-sigma edge (measured: ~6% of these rows)
     assert amb.mean() < 0.1
-    _say("million: 3-bounce transfer")
+    say("million: 3-bounce transfer")
     t = prt.precompute_transfer(sc, bvh, params, check=True)
     d = prt.precompute_transfer(sc, bvh, prt.TransferParams(num_dirs=S, sh_bands=bands))
     assert torch.isfinite(t).all()
     gain = (t[:, :, 0] - d[:, :, 0]).double()
     assert gain.min().item() > -2e-5 and gain.max().item() > 1e-2
-    _say(f"million index: {int((got >= 0).sum())} indexed rays in the sample, max DC gain {gain.max().item():.3f}")
+    say(f"million index: {int((got >= 0).sum())} indexed rays in the sample, max DC gain {gain.max().item():.3f}")
 
 
 def test_relight3m_full(prt, oracle_mod):
@@ -175,13 +169,13 @@ def test_relight3m_full(prt, oracle_mod):
     rows_t = torch.tensor(rows, device="cuda")
     bounds = {("f32", "f32"): 2e-6, ("bf16", "f16"): 1e-2, ("f16", "f16"): 1e-2, ("bf16", "f32"): 1e-2}
     for (tdt, odt), bound in bounds.items():
-        _say(f"relight3m: {tdt} -> {odt}")
+        say(f"relight3m: {tdt} -> {odt}")
         t = T if tdt == "f32" else prt.pack(T, tdt)
         out = prt.relight(t, L, out_dtype=odt)
         got = out[rows_t].double().cpu().numpy()
         rel = np.abs(got - ref) / scale
         assert rel.max() <= bound, (tdt, odt, rel.max())
-        _say(f"relight3m {tdt} -> {odt}: max rel err {rel.max():.2e}, mean {rel.mean():.2e}")
+        say(f"relight3m {tdt} -> {odt}: max rel err {rel.max():.2e}, mean {rel.mean():.2e}")
         del out
 
 
@@ -215,12 +209,12 @@ def test_grad200k_sampled_gaussians(prt):
     from oracle.grad import gaussian_param_grads
     w, scene = _workload_scene("grad200k")
     n = scene["means"].shape[0]
-    _say("grad200k: forward + backward")
+    say("grad200k: forward + backward")
     g, dT = _grad200k_adjoint(prt, scene, w)
     picks = np.random.default_rng(105).choice(n, 8, replace=False)
     refs = []
     for j in picks:
-        _say(f"grad200k: oracle for Gaussian {j}")
+        say(f"grad200k: oracle for Gaussian {j}")
         refs.append(gaussian_param_grads(scene, int(j), w["num_dirs"], w["bands"], dT))
     for key in ("opacity", "log_scales", "quats", "means", "normals"):
         scale = max(np.abs(np.asarray(r["grads"][key])).max() for r in refs)
@@ -229,7 +223,7 @@ def test_grad200k_sampled_gaussians(prt):
             got = np.asarray(g[key][j], dtype=np.float64)
             tol = 1e-3 * np.maximum(np.abs(ref), 1e-2 * scale) + np.asarray(r["allow"][key])
             assert (np.abs(got - ref) <= tol).all(), (key, int(j), got, ref, r["allow"][key])
-        _say(f"grad200k {key}: ok (largest |g| {scale:.3e})")
+        say(f"grad200k {key}: ok (largest |g| {scale:.3e})")
 
 
 def test_grad200k_central_differences(prt, oracle_mod):
@@ -251,7 +245,7 @@ def test_grad200k_central_differences(prt, oracle_mod):
     w, scene = _workload_scene("grad200k")
     n = scene["means"].shape[0]
     S, bands = w["num_dirs"], w["bands"]
-    _say("grad200k FD: forward + backward")
+    say("grad200k FD: forward + backward")
     g, dT = _grad200k_adjoint(prt, scene, w)
     dirs, Y = oracle_mod.tables(S, 0, bands)
     wq = 4.0 * math.pi / S
@@ -263,7 +257,7 @@ def test_grad200k_central_differences(prt, oracle_mod):
     D = torch.from_numpy(dirs)
     for q, j in enumerate(rng.choice(n, 16, replace=False)):
         j = int(j)
-        _say(f"grad200k FD: Gaussian {q + 1} of 16 (index {j})")
+        say(f"grad200k FD: Gaussian {q + 1} of 16 (index {j})")
         # rays of other sources that reach j (FP64, every source)
         with torch.no_grad():
             R = _rotation(torch.from_numpy(scene["quats"][j][None]))[0]
@@ -304,7 +298,7 @@ def test_grad200k_central_differences(prt, oracle_mod):
                     vals.append(loss_rays(pert))
                 est.append((vals[0] - vals[1]) / (2 * h))
             results.append((key, idx, est, float(g[key][idx])))
-        _say(f"grad200k FD: Gaussian {j}, {len(ii)} rays through it, {len(own)} of its own")
+        say(f"grad200k FD: Gaussian {j}, {len(ii)} rays through it, {len(own)} of its own")
     checked = 0
     for key, idx, est, got in results:
         scale = max(abs(est[1]), 1e-2 * max(abs(e[1]) for k, _, e, _ in results if k == key), 1e-12)
@@ -313,7 +307,7 @@ def test_grad200k_central_differences(prt, oracle_mod):
         checked += 1
         rich = (16.0 * est[1] - est[0]) / 15.0
         assert abs(got - rich) <= 1e-3 * scale, (key, idx, got, est)
-    _say(f"grad200k FD: {checked} of {len(results)} parameters checked, by input: "
+    say(f"grad200k FD: {checked} of {len(results)} parameters checked, by input: "
          f"{ {k: sum(1 for r in results if r[0] == k) for k in dict(comps)} }")
     # thousands of rays reach each Gaussian, so about half the parameters have
     # a cut-off decision inside +-h and are skipped

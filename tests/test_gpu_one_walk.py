@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import scenegen
-from helpers import as_f32, assert_ray_vis, assert_transfer_parity
+from helpers import as_f32, assert_ray_vis, assert_transfer_parity, say
 
 pytestmark = pytest.mark.gpu
 
@@ -19,10 +19,6 @@ def prt():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     import paper_2408_03538_amd as p
     return p
-
-
-def _say(msg):
-    print(msg, flush=True)
 
 
 def _small_million_like(seed=21):
@@ -63,7 +59,7 @@ def test_one_walk_parity_sampled(prt, oracle_mod):
     t1, vis1, f1 = _run(prt, sc, bvh, _params(prt, S, bands, R), want_vis=True)
     assert not f1 & _lib.FLAG_RECORDS_DEFERRED
     src = np.random.default_rng(3).choice(n, 200, replace=False)
-    _say("one walk: oracle on 200 sources")
+    say("one walk: oracle on 200 sources")
     ref = oracle_mod.full_transfer(scene, S, bands, 1, sources=src, want_allow=True)
     err = assert_transfer_parity(t1[src], ref["t"], ref["allow"], what="one-walk transfer")
     assert np.abs(ref["t_ind"]).max() > 1e-2
@@ -78,7 +74,7 @@ def test_one_walk_parity_sampled(prt, oracle_mod):
     # each product rounded differently (a few ulps per factor); a ray at T_eps may be 0 on one side only
     assert (dv <= 1e-5 + 1e-5 * vis2[traced]).mean() > 0.9999
     assert (dv <= 1.01e-4 + 1e-5 * vis2[traced]).all()
-    _say(f"one walk: max |dt| = {err:.2e} vs oracle; {rays} rays within their range ({wide} near a threshold); "
+    say(f"one walk: max |dt| = {err:.2e} vs oracle; {rays} rays within their range ({wide} near a threshold); "
          f"max |t1 - t2| = {np.abs(t1 - t2).max():.2e} vs two walks")
 
 
@@ -101,10 +97,10 @@ def test_one_walk_million_launch_shape(prt, oracle_mod):
     t2, _, _ = _run(prt, sc, bvh, _params(prt, S, 4, 0, **kw))
     assert np.abs(t1 - t2).max() <= 1e-4
     src = np.random.default_rng(43).choice(n, 24, replace=False)
-    _say("one walk, million shape: oracle on 24 sources")
+    say("one walk, million shape: oracle on 24 sources")
     ref = oracle_mod.full_transfer(scene, S, 4, 1, sources=src, want_allow=True)
     err = assert_transfer_parity(t1[src], ref["t"], ref["allow"], what="one-walk transfer")
-    _say(f"one walk, million shape: max |dt| = {err:.2e}")
+    say(f"one walk, million shape: max |dt| = {err:.2e}")
 
 
 @pytest.mark.parametrize("fraction,spw", [(0.3, 0), (0.0, 0), (0.3, 16), (0.3, 2)])
@@ -157,11 +153,11 @@ def test_one_walk_many_faint_hits(prt, oracle_mod):
     t2, _, f2 = _run(prt, sc, bvh, _params(prt, S, bands, st["blended_hits"] // 4))
     assert f2 & _lib.FLAG_RECORDS_DEFERRED
     src = np.random.default_rng(4).choice(n, 60, replace=False)
-    _say("one walk, faint cloud: oracle on 60 sources")
+    say("one walk, faint cloud: oracle on 60 sources")
     ref = oracle_mod.full_transfer(scene, S, bands, 1, sources=src, want_allow=True)
     for t, what in ((t1, "one walk"), (t2, "one walk, deferred items")):
         err = assert_transfer_parity(t[src], ref["t"], ref["allow"], what=what)
-        _say(f"faint cloud, {what}: max |dt| = {err:.2e}")
+        say(f"faint cloud, {what}: max |dt| = {err:.2e}")
     assert np.abs(t1 - t2).max() <= 1e-5 * (1.0 + np.abs(t1).max())
 
 
@@ -196,7 +192,7 @@ def test_one_walk_work_counts(prt):
     assert one["traced_rays"] == two["traced_rays"] == direct["traced_rays"]
     assert abs(one["blended_hits"] - two["blended_hits"]) <= 1e-3 * two["blended_hits"]
     assert one["box_tests"] < two["box_tests"] + direct["box_tests"]
-    _say(f"box tests per ray: one walk {one['box_tests'] / one['traced_rays']:.1f}, two walks "
+    say(f"box tests per ray: one walk {one['box_tests'] / one['traced_rays']:.1f}, two walks "
          f"{two['box_tests'] / two['traced_rays']:.1f} + {direct['box_tests'] / direct['traced_rays']:.1f}")
 
 
@@ -220,7 +216,7 @@ def test_one_walk_index_matrix(prt, oracle_mod, S, shape):
     differ = idx1 != idx2
     assert differ.mean() < 1e-3
     src = np.random.default_rng(44).choice(n, 24, replace=False)
-    _say(f"one-walk index matrix S = {S}: oracle on 24 sources")
+    say(f"one-walk index matrix S = {S}: oracle on 24 sources")
     ref_idx, amb = oracle_mod.index_matrix(scene, S, sources=src)
     assert np.array_equal(idx1[src][~amb], ref_idx[~amb])
     t1, _, _ = _run(prt, sc, bvh, p1)
@@ -228,5 +224,5 @@ def test_one_walk_index_matrix(prt, oracle_mod, S, shape):
     same = ~differ.any(axis=1)
     assert same.mean() > 0.99
     assert np.abs(t1 - t2)[same].max() <= 1e-4
-    _say(f"one-walk index matrix S = {S}: {differ.sum()} of {differ.size} entries differ from two walks; "
+    say(f"one-walk index matrix S = {S}: {differ.sum()} of {differ.size} entries differ from two walks; "
          f"max |dt| where they agree {np.abs(t1 - t2)[same].max():.2e}")
