@@ -60,9 +60,9 @@ FLOPS_PER_PRIM_TEST = 70
 # project_kernel<16>, add_parts_kernel and the deferred-item pass), summed
 # (profiles/one_walk_million_counters.md).
 MEASURED = {
-    "direct_surface100k": {"sources_sha256_16": "c74ce41ef3edc0ca", "bytes_per_launch": 7.2786e9,
+    "direct_surface100k": {"sources_sha256_16": "0acb27b42cfd1486", "bytes_per_launch": 7.2786e9,
                            "valu_instructions_per_launch": 1.0735e10},
-    "one_walk_million": {"sources_sha256_16": "c74ce41ef3edc0ca", "bytes_per_launch": 5.2305e12,
+    "one_walk_million": {"sources_sha256_16": "0acb27b42cfd1486", "bytes_per_launch": 5.2305e12,
                          "valu_instructions_per_launch": 1.3882e12},
 }
 KERNEL_SOURCES = ["paper_2408_03538_amd/csrc/transfer.hip", "paper_2408_03538_amd/csrc/trace.hpp",

@@ -8,10 +8,12 @@
 // stratum tiles, Morton order inside, so aligned runs stay in one octant and
 // a compact patch of the sphere); lane l traces source l / D along direction
 // l % D.  The direction batches of a group are shared among Q waves, issued
-// part-major, so that the waves in flight trace the same directions.  Neighbouring origins share the Gaussians around them, nearby
-// directions share the far field.  Each ray's weight T max(n . w, 0) is
-// stored, and a second kernel projects every source's S weights onto SH in
-// FP64, in direction order, so the transfer does not depend on the split.
+// part-major, so that the waves in flight trace the same directions.
+// Neighbouring origins share the Gaussians around them, nearby directions
+// share the far field.  Each ray's weight T max(n . w, 0) is
+// stored, and a second kernel projects every source's S weights onto SH
+// with compensated FP32 sums, in direction order, so the transfer does not
+// depend on the split.
 // Small scenes use the "fan" split instead (one source per wave, its
 // hemisphere directions compacted over the lanes) to fill the GPU.
 #include "trace.hpp"
