@@ -794,13 +794,62 @@ def cpu_baseline(arr, params, seconds):
         model = "unknown"
     passes = 2 if params.bounces else 1
     what = "direct pass + bounce walk" if params.bounces else "direct pass"
+    try:
+        other = cpu_oracle_rates(threads)
+    except Exception as e:   # context figures only: the line is still printed, with the error
+        log(f"cpu oracle rates of the other workloads failed: {e!r}")
+        other = {"error": repr(e)}
     return {"value": value, "unit": "Grays/s (nominal N*S rays per second)", "cores": threads, "kind": "oracle",
             "sample": f"{done} random sources of the {n}-splat workload ({done * S} nominal rays, {traced} traced, "
                       f"{what}: {t_direct:.1f} s + {t_bounce:.1f} s), each traced ray tested against all {n} "
                       f"Gaussians per pass, FP64",
             "ray_gaussian_tests_per_s": round(passes * traced * (n - 1) / elapsed, 1),
             "direct_pass_traced_rays_per_s": round(traced / t_direct, 1),
-            "cpu_model": model}
+            "cpu_model": model,
+            "other_workloads": other}
+
+
+def cpu_oracle_rates(threads, sampled_sources=32):
+    """The oracle's rates on the other workloads, a few seconds each (context
+    for their GPU figures, not targets): the 1000-splat cloud in full and a
+    seeded sample of sources of the 100k surface and of the 200k gradient
+    workload (direct pass: every traced ray against all N Gaussians, FP64),
+    and the FP64 autograd gradient of the 500-splat subset of the 200k scene
+    (transfer + relight + L2 loss, every input)."""
+    import numpy as np
+
+    import oracle
+    import scenegen
+    from oracle.grad import loss_and_grads
+
+    out = {}
+    for name, full in (("cloud1k", True), ("surface100k", False), ("grad200k", False)):
+        w = scenegen.workload(name)
+        scene = w["scene"]
+        n, S = scene["means"].shape[0], w["num_dirs"]
+        src = np.arange(n) if full else np.random.default_rng(11).choice(n, sampled_sources, replace=False)
+        dirs = oracle.directions(S)
+        traced = int((scene["normals"][src] @ dirs.T > 0.0).sum())
+        t0 = time.perf_counter()
+        oracle.direct_transfer(scene, S, w["bands"], sources=src, margins=None, threads=threads)
+        sec = time.perf_counter() - t0
+        out[name] = {"sample": f"{'all' if full else 'random'} {len(src)} sources of {n}, S={S}, direct pass, "
+                               f"{traced} traced rays, {sec:.2f} s",
+                     "grays_per_s_nominal": len(src) * S / sec / 1e9,
+                     "traced_rays_per_s": round(traced / sec, 1),
+                     "ray_gaussian_tests_per_s": round(traced * (n - 1) / sec, 1)}
+        log(f"cpu oracle {name}: {traced / sec:.0f} traced rays/s")
+    w = scenegen.workload("grad200k")
+    sub = scenegen.seeded_subset(w["scene"], 500, scenegen.SEED_FD_PICK)
+    tgt = scenegen.colour_targets(500, 1, scenegen.SEED_TARGET + 4)
+    t0 = time.perf_counter()
+    loss_and_grads(sub, w["num_dirs"], w["bands"], w["light"], tgt)
+    sec = time.perf_counter() - t0
+    out["grad200k_subset500"] = {"sample": f"the 500-splat subset of the 200k scene, S={w['num_dirs']}, FP64 "
+                                           f"autograd of transfer + relight + L2 loss, {sec:.2f} s",
+                                 "seconds_per_gradient": round(sec, 3)}
+    log(f"cpu oracle gradient, 500-splat subset: {sec:.1f} s")
+    return out
 
 
 if __name__ == "__main__":
