@@ -224,7 +224,8 @@ prtgs_status prtgs_precompute_transfer(const prtgs_gaussians* g /* host */, cons
 /* cover larger scenes with several source ranges.  Calls that overlap on    */
 /* one GPU share its scratch and race: serialise them (one stream, or        */
 /* events).  bounces != 0 returns PRTGS_ERR_UNSUPPORTED.  flags (device word,*/
-/* may be NULL): cleared, then receives the call's device flag bits.  The    */
+/* may be NULL): cleared, then receives the call's device flag bits; with    */
+/* NULL they go to the scratch's own flag word and are not reported.  The    */
 /* result equals prtgs_precompute_transfer's for the same arguments.         */
 #define PRTGS_NOALLOC_SCRATCH_MIB 64
 prtgs_status prtgs_precompute_transfer_noalloc(const prtgs_gaussians* g /* host */, const void* bvh,
