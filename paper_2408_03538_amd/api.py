@@ -221,6 +221,39 @@ def precompute_transfer(scene: Scene, bvh: Bvh, params: TransferParams, first: i
     return (out, vis) if want_vis else out
 
 
+def precompute_transfer_noalloc(scene: Scene, bvh: Bvh, params: TransferParams, first: int = 0,
+                                count: int | None = None, out: torch.Tensor | None = None,
+                                vis: torch.Tensor | None = None, flags: torch.Tensor | None = None,
+                                check: bool = False):
+    """The direct transfer (params.bounces == 0) through the library's
+    no-allocation entry point: no workspace; its scratch is a static device
+    array inside the library, shared by every call on the GPU (serialise
+    overlapping calls).  Pass ``out`` [n, 1, K], ``vis`` [n, S] (optional) and
+    ``flags`` (int32 [1], optional) preallocated for a call that allocates
+    nothing; ``out`` and, with ``check``, ``flags`` are allocated here if
+    missing.  Returns ``out``."""
+    lib = _lib.load()
+    n = scene.n
+    count = n - first if count is None else count
+    g = scene.c_struct()
+    d = params.c_struct()
+    if out is None:
+        out = torch.zeros((n, 1, params.K), dtype=F32, device=scene.device)
+    if out.dtype != F32 or tuple(out.shape) != (n, 1, params.K) or not out.is_contiguous():
+        raise ValueError("out must be contiguous float32 [n, 1, K]")
+    if vis is not None and (vis.dtype != F32 or tuple(vis.shape) != (n, params.num_dirs) or not vis.is_contiguous()):
+        raise ValueError("vis must be contiguous float32 [n, num_dirs]")
+    if flags is None and check:
+        flags = torch.zeros(1, dtype=torch.int32, device=scene.device)
+    if flags is not None and (flags.dtype != torch.int32 or flags.numel() < 1):
+        raise ValueError("flags must be an int32 tensor of at least one element")
+    _lib.check(lib.prtgs_precompute_transfer_noalloc(ctypes.byref(g), _ptr(bvh.buffer), ctypes.byref(d), first,
+                                                     count, _ptr(out), _ptr(vis), _ptr(flags), _stream()))
+    if check:
+        check_flags(flags, "precompute_transfer_noalloc")
+    return out
+
+
 def index_matrix(scene: Scene, bvh: Bvh, params: TransferParams, workspace: Workspace | None = None,
                  check: bool = False) -> torch.Tensor:
     """The paper's index matrix [n, S] int32 (original indices, -1 = none)."""

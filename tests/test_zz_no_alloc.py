@@ -108,3 +108,28 @@ def test_noalloc_rejects_oversized_call(prt):
             None, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
+
+
+def test_noalloc_python_binding(prt):
+    """The binding of the same name (argument marshalling only): with out, vis
+    and flags preallocated, then with out allocated for a leaf range, each
+    equal to the workspace entry point; bounces != 0 is refused."""
+    import torch
+    print("no-alloc binding: surface 3000, S = 128", flush=True)
+    scene = as_f32(scenegen.surface_scene(3000, 75))
+    sc = prt.Scene.from_arrays(scene)
+    bvh = prt.build_bvh(sc, check=True)
+    params = prt.TransferParams(num_dirs=128, sh_bands=4)
+    ref, vref = prt.precompute_transfer(sc, bvh, params, want_vis=True, check=True)
+    out = torch.full((sc.n, 1, 16), 7.0, dtype=torch.float32, device="cuda")
+    vis = torch.full((sc.n, 128), 7.0, dtype=torch.float32, device="cuda")
+    flags = torch.full((1,), 12345, dtype=torch.int32, device="cuda")
+    got = prt.precompute_transfer_noalloc(sc, bvh, params, out=out, vis=vis, flags=flags, check=True)
+    assert got is out
+    assert torch.equal(out, ref) and torch.equal(vis, vref)
+    assert int(flags.item()) == 0
+    ref2 = prt.precompute_transfer(sc, bvh, params, first=500, count=1000)
+    got2 = prt.precompute_transfer_noalloc(sc, bvh, params, first=500, count=1000, check=True)
+    assert torch.equal(got2, ref2)
+    with pytest.raises(prt.PrtgsError):
+        prt.precompute_transfer_noalloc(sc, bvh, prt.TransferParams(num_dirs=128, sh_bands=4, bounces=1))
